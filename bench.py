@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Throughput of the NEDNER reconstruction operator on one MI355X.
+
+One step = one forward execute of the whole operator (spread, lateral FFTs and
+deconvolution, NER column FFT + gather + weight, inverse 3D FFT) on one
+resident batch of synthetic sensor data. Prints ONE JSON line:
+
+  value        non-uniform points per second, M * Nt / t_step, in Mpts/s
+  roofline     the slowest kernel against its bound (HBM bytes or ALU flops),
+               timed live with HIP events on the execute stream
+  cpu_baseline the FP64 oracle timed on the host on the same workload
+  fp64_plain   the same operator in FP64 on the GPU, and the FP32 speedup
+
+Inputs: 128x128 jittered sensors (+/-0.45 pitch), 512 samples, 10 random balls
+and 1 % noise, output 128x128x256 (the FP32-vs-plain comparison workload).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NEDNER-NUFFT recon Mpts/s & %HBM roofline, FP32 vs FP64 plain at rel err 1e-5"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
+FP32_VECTOR_TFLOPS = 157.3
+
+WORKLOADS = {
+    "c2": "128x128 sensors jittered +/-0.45 pitch, 512 samples, 10 balls + 1% noise -> 128x128x256",
+    "c3": "65536 sensors 4x denser near the centre, 1024 samples, 30 balls + 5 bead chains -> 256x256x512",
+    "c5": "192x192 sensors jittered +/-0.4 pitch, 768 samples, 20 balls + 1% noise -> 192x192x384",
+    "c1": "32x32 sensors jittered +/-0.4 pitch, 128 samples, one ball -> 32x32x64",
+}
+
+
+def stage_model(p, info, prec):
+    """Algorithmic bytes and flops of each forward stage (one launch each)."""
+    rs = 8 if prec == "fp64" else 4
+    cs = 2 * rs
+    M, Nt, N1, N2, N3 = p.m, p.nt, p.n1, p.n2, p.n3
+    n1, n2, ntt = info["n1_os"], info["n2_os"], info["nt_os"]
+    K2, J1, W = N2 // 2 + 1, N1 + 1, 12
+    return {
+        "spread": dict(bytes=rs * M * Nt + rs * n1 * n2 * Nt, flops=2 * W * W * M * Nt),
+        "lat_a": dict(bytes=rs * n1 * n2 * Nt + cs * n1 * K2 * Nt,
+                      flops=int(2.5 * n1 * n2 * Nt * math.log2(n2))),
+        "lat_b": dict(bytes=cs * n1 * K2 * Nt + cs * K2 * J1 * Nt,
+                      flops=int(5 * n1 * K2 * Nt * math.log2(n1))),
+        "column": dict(bytes=cs * K2 * J1 * Nt + cs * K2 * J1 * N3,
+                       flops=int(K2 * J1 * (5 * ntt * math.log2(ntt) + (N3 + 1) * 4 * W
+                                            + 5 * N3 * math.log2(N3)))),
+        "pass_c": dict(bytes=cs * K2 * J1 * N3 + cs * K2 * N1 * N3,
+                       flops=int(5 * K2 * N1 * N3 * math.log2(N1))),
+        "pass_d": dict(bytes=cs * K2 * N1 * N3 + rs * N1 * N2 * N3,
+                       flops=int(2.5 * N1 * N2 * N3 * math.log2(N2))),
+    }
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1501_02946_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1501_02946_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, prec, stage):
+    """HBM bytes per launch from committed rocprofv3 counters, if still current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    rec = d.get(f"{workload}:{prec}:{stage}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes")
+
+
+def time_steps(torch, plan, g, out, steps, warmup, profile=False):
+    import ctypes
+    import paper_1501_02946_amd as N
+    for _ in range(warmup):
+        plan.forward(g, out=out)
+    torch.cuda.synchronize()
+    if profile:
+        N._check(N.lib().nedner_profile_begin(plan._plan, steps))
+    stream = torch.cuda.current_stream(plan.device)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        plan.forward(g, out=out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    stages = None
+    if profile:
+        arr = (ctypes.c_double * 16)()
+        ns = ctypes.c_int(0)
+        names = ctypes.c_char_p()
+        N._check(N.lib().nedner_profile_end(plan._plan, arr, 16, ctypes.byref(ns), ctypes.byref(names)))
+        stages = dict(zip(names.value.decode().split(","), [arr[i] for i in range(ns.value)]))
+    return ms, stages
+
+
+def cpu_baseline(p, leg_limit_s=60.0):
+    """The FP64 oracle on the host: full forward operator on the same workload."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    geo = O.geometry(**p.geometry_kwargs())
+    t = time.perf_counter()
+    F = O.spectrum(p.xy, p.h, p.g, geo)
+    v = O.volume_from_spectrum(F)
+    dt = time.perf_counter() - t
+    return v, dict(value=p.m * p.nt / dt / 1e6, unit="Mpts/s", cores=int(threads), kind="oracle",
+                   seconds=round(dt, 3),
+                   sample=(f"the full workload ({p.m} sensors x {p.nt} samples -> "
+                           f"{p.n1}x{p.n2}x{p.n3}): NED as BLAS GEMMs on {threads} threads, "
+                           "NER by Horner's rule (numpy, one thread), numpy ifftn"))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp32_plain", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU split of the "
+              "operator is a design note, not part of this build", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1501_02946_amd as N
+    import synth
+
+    p = synth.config(a.workload)
+    plan = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0,
+                  precision=a.precision)
+    g = torch.as_tensor(p.g, dtype=plan.dtype, device=plan.device).contiguous()
+    out = torch.empty((p.n1, p.n2, p.n3), dtype=plan.dtype, device=plan.device)
+
+    ms, _ = time_steps(torch, plan, g, out, a.steps, a.warmup)
+    _, stages = time_steps(torch, plan, g, out, a.steps, 1, profile=True)
+    vol = out.cpu().numpy()
+    points = p.m * p.nt
+    value = points / (ms / 1e3) / 1e6
+
+    model = stage_model(p, plan.info, a.precision)
+    stage_rep = {}
+    for name, t in stages.items():
+        m = model.get(name, {})
+        gbs = m.get("bytes", 0) / (t / 1e3) / 1e9 if t > 0 else 0.0
+        stage_rep[name] = dict(ms=round(t, 5), alg_bytes=m.get("bytes"), alg_flops=m.get("flops"),
+                               hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+    dom = max(stages, key=stages.get)
+    tdom = stages[dom] / 1e3
+    if dom == "spread":
+        # the spread is a W*W-tap multiply-add per (sensor, sample): ALU bound;
+        # the compensated and FP64 paths accumulate with FP64 FMAs
+        peak = FP64_VECTOR_TFLOPS if a.precision in ("fp32c", "fp64") else FP32_VECTOR_TFLOPS
+        ach = model[dom]["flops"] / tdom / 1e12
+        roof = dict(bound="alu", achieved=round(ach, 3), peak=peak, unit="TFLOP/s",
+                    frac=round(ach / peak, 4))
+    else:
+        ach = model[dom]["bytes"] / tdom / 1e9
+        roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4))
+    roof["kernel"] = dom
+    roof["ms"] = round(stages[dom], 5)
+    roof["traffic"] = measured_traffic(a.workload, a.precision, dom)
+
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {WORKLOADS[a.workload]}", "sensors": p.m,
+                   "nt": p.nt, "volume": [p.n1, p.n2, p.n3], "precision": a.precision,
+                   "window_taps": 12, "oversampling": 2},
+        "volumes_per_s": round(1e3 / ms, 2),
+        "roofline": roof,
+        "stages": stage_rep,
+    }
+    if not a.no_fp64 and a.precision != "fp64":
+        p64 = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0, precision="fp64")
+        g64 = torch.as_tensor(p.g, dtype=torch.float64, device=plan.device).contiguous()
+        o64 = torch.empty((p.n1, p.n2, p.n3), dtype=torch.float64, device=plan.device)
+        ms64, _ = time_steps(torch, p64, g64, o64, a.steps, a.warmup)
+        res["fp64_plain"] = dict(ms_per_step=round(ms64, 5), value=round(points / (ms64 / 1e3) / 1e6, 2),
+                                 fp32_speedup=round(ms64 / ms, 3))
+        vol64 = o64.cpu().numpy()
+        del p64
+    else:
+        vol64 = None
+    if not a.no_cpu_baseline:
+        vref, cb = cpu_baseline(p)
+        res["cpu_baseline"] = cb
+        nrm = float(np.linalg.norm(vref))
+        res["rel_l2_vs_oracle"] = float(np.linalg.norm(vol.astype(np.float64) - vref) / nrm)
+        if vol64 is not None:
+            res["fp64_plain"]["rel_l2_vs_oracle"] = float(np.linalg.norm(vol64 - vref) / nrm)
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

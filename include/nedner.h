@@ -1,0 +1,183 @@
+/*
+ * nedner.h - C-ABI of the NEDNER-NUFFT planar photoacoustic reconstruction
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the discretised exact inversion formula for sensors
+ * on a plane (Schmid et al., arXiv 1501.02946, eq. (1) and its non-equispaced
+ * discretisation eq. (5), Sec. 2) with the three-step NEDNER-NUFFT of Sec. 3:
+ *
+ *   1. NED: a 2D non-uniform FFT over the sensor positions (eq. (9)-(10)):
+ *      Gaussian spreading of every time sample onto an oversampled lateral
+ *      grid, a lateral FFT and deconvolution;
+ *   2. NER: a 1D non-uniform FFT in time evaluated at the frequencies
+ *      omega = c sign(kz) |K| (eq. (6)-(8)), followed by the weight of eq. (1);
+ *   3. an inverse 3D FFT to the image (Sec. 3, last step).
+ *
+ * and the exact transpose of that pipeline (the adjoint).
+ *
+ * Conventions (all physical units):
+ *   sensor m at y_m = (y1, y2) on the plane z = 0 with detector area h_m,
+ *   data g[m][n] recorded at t_n = t0 + n*dt, n = 0..nt-1, sound speed c;
+ *   output voxel (i1, i2, i3) at (a1 + i1*d1, a2 + i2*d2, i3*d3); the lateral
+ *   aperture [a_i, a_i + n_i*d_i) is periodic; d3 = 0 selects c*nt*dt/n3.
+ *   Modes j_i in {-n_i/2..n_i/2-1}, k_i = 2 pi j_i/(n_i d_i),
+ *   l in {-n3/2..n3/2-1}, kz = 2 pi l/(n3 d3), omega = c sign(l) |K|;
+ *   W = 2c|kz|/|K| (l != 0), W(0,0) = 2c, W(j != 0, 0) = 0;
+ *   F(j,l) = (dt/d3) W sum_n exp(-i omega t_n) sum_m h_m/(d1 d2) g[m][n] exp(-i k.(y_m - a));
+ *   volume f = Re IDFT_3(F) / (n1 n2 n3).
+ *
+ * Layouts (row-major, last index fastest):
+ *   data g      : [m][nt]            (FP64 plans: double, otherwise float)
+ *   volume      : [n1][n2][n3]       real, depth fastest
+ *   spectrum    : [n1][n2][n3]       complex (re, im interleaved), FFT order:
+ *                                    index k along an axis holds mode k mod n
+ *   stage grid  : [sigma*n1][sigma*n2][nt] real, the spread grid (debug)
+ *
+ * Ownership: plan creation copies every host array, so the caller may free
+ * them on return. The plan owns its small device tables and frees them in
+ * nedner_destroy. Large intermediates live in a caller-provided device
+ * workspace (nedner_set_workspace) that must outlive every enqueued execute
+ * and must not be shared by two executes in flight. Device pointers passed to
+ * execute calls belong to the caller and must be on the plan's device.
+ * Execute calls are asynchronous on the given HIP stream (NULL = default).
+ *
+ * Errors: no call aborts or throws across this interface. Each returns a
+ * status; nedner_last_error() gives a thread-local message for the last
+ * failing call on that thread. After NEDNER_E_HIP a plan accepts only
+ * nedner_destroy. Plans are independent; one plan is not reentrant.
+ */
+#ifndef NEDNER_H
+#define NEDNER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NEDNER_VERSION 100
+
+typedef struct nedner_plan_s* nedner_plan;
+
+typedef enum {
+  NEDNER_OK = 0,
+  NEDNER_E_ARG = 1,          /* invalid descriptor or argument */
+  NEDNER_E_ALIAS = 2,        /* max |omega| dt >= pi and ALLOW_ALIAS not set */
+  NEDNER_E_OOM = 3,          /* device or host allocation failed */
+  NEDNER_E_WORKSPACE = 4,    /* no workspace, or one that is too small */
+  NEDNER_E_HIP = 5,          /* a HIP runtime call failed; plan is now unusable */
+  NEDNER_E_UNSUPPORTED = 6,  /* valid but not implemented (FFT size, kind) */
+  NEDNER_E_STATE = 7         /* plan unusable after an earlier HIP error */
+} nedner_status;
+
+typedef enum {
+  NEDNER_FP64 = 0,              /* every step in double */
+  NEDNER_FP32 = 1,              /* float data and arithmetic, double argument reduction */
+  NEDNER_FP32_COMPENSATED = 2,  /* as FP32, spreading accumulated in double registers */
+  NEDNER_FP32_PLAIN = 3         /* float everywhere, arguments included */
+} nedner_precision;
+
+typedef enum {
+  NEDNER_VOLUME_REAL = 0,       /* the image f, [n1][n2][n3] real */
+  NEDNER_SPECTRUM_COMPLEX = 1,  /* F(j,l), [n1][n2][n3] complex, FFT order */
+  NEDNER_STAGE_GRID = 2         /* the spread grid (forward) / its transpose (adjoint) */
+} nedner_kind;
+
+#define NEDNER_ALLOW_ALIAS 1u      /* accept max |omega| dt >= pi */
+#define NEDNER_WRAP_POSITIONS 2u   /* wrap positions into the periodic aperture */
+#define NEDNER_DETERMINISTIC 4u    /* accepted; every path is bitwise deterministic */
+#define NEDNER_NO_AUTOTUNE 8u      /* keep the built-in launch shapes */
+
+/* Plan descriptor. Fill with nedner_desc_init, then set the fields. */
+typedef struct {
+  int64_t m;            /* number of sensors, >= 1 */
+  const double* xy;     /* host, [m][2] positions (y1, y2) */
+  const double* h;      /* host, [m] detector areas; NULL => n1 d1 n2 d2 / m each */
+  int64_t nt;           /* time samples, even, >= 2 */
+  double t0, dt, c;     /* first sample time, time step > 0, sound speed > 0 */
+  int32_t n1, n2, n3;   /* output voxels, each even and >= 2 */
+  double a1, a2;        /* aperture origin */
+  double d1, d2, d3;    /* voxel steps; d1, d2 > 0; d3 = 0 => c nt dt / n3 */
+  int32_t prec;         /* nedner_precision */
+  int32_t w;            /* window taps per dimension, even, 2..16 (default 12 = 2K, K = 6) */
+  double sigma;         /* oversampling factor (default 2); sigma*n1, sigma*n2,
+                           sigma*nt must be even integers */
+  double tau_scale;     /* Gaussian width scale relative to Greengard-Lee (default 1) */
+  uint32_t flags;       /* NEDNER_* flags */
+  int32_t rows_per_wave;   /* spreading sweep length; 0 = automatic */
+  int32_t time_per_lane;   /* time samples per lane in spreading (1, 2, 4); 0 = automatic */
+} nedner_desc;
+
+/* Sizes a descriptor implies; filled by nedner_query (host only, no HIP). */
+typedef struct {
+  int32_t n1_os, n2_os, nt_os;   /* oversampled lateral grid and time FFT length */
+  int32_t columns;               /* NER columns: (n1 + 1) * (n2 / 2 + 1) */
+  int32_t segments;              /* spreading sweep segments along the first axis */
+  int32_t rows_per_wave;         /* rows per sweep segment */
+  int32_t time_per_lane;         /* time samples per lane in spreading */
+  int32_t pad0;
+  size_t workspace_bytes;        /* device workspace an execute needs */
+  size_t table_bytes;            /* device tables the plan allocates */
+  double beta;                   /* Gaussian exponent: phi(x) = exp(-beta x^2), x in grid units */
+  double max_abs_theta;          /* max |omega| dt over the mode set (alias check: < pi) */
+  int64_t list_entries;          /* (sensor, column) pairs in the spreading lists */
+} nedner_info;
+
+/* Fill a descriptor with the defaults (w = 12, sigma = 2, tau_scale = 1, FP32). */
+void nedner_desc_init(nedner_desc* desc);
+
+/* Host-only validation of a descriptor (no HIP call). Returns NEDNER_E_ARG,
+   NEDNER_E_ALIAS, NEDNER_E_UNSUPPORTED or NEDNER_OK. */
+nedner_status nedner_validate(const nedner_desc* desc);
+
+/* Host-only: validate and report the sizes the plan would use. */
+nedner_status nedner_query(const nedner_desc* desc, nedner_info* info);
+
+/* Build a plan on `device`: FP64 sensor geometry, window weights, spreading
+   lists, deconvolution and twiddle tables; uploads them on `stream`. */
+nedner_status nedner_plan_create(const nedner_desc* desc, int device, void* stream,
+                                 nedner_plan* plan);
+
+/* Batched plan: `count` independent problems run together by the *_many calls. */
+nedner_status nedner_plan_create_many(const nedner_desc* descs, int count, int device,
+                                      void* stream, nedner_plan* plan);
+
+nedner_status nedner_plan_info(nedner_plan plan, nedner_info* info);
+nedner_status nedner_workspace_size(nedner_plan plan, size_t* bytes);
+/* Attach a device workspace of at least nedner_workspace_size bytes (256-byte aligned). */
+nedner_status nedner_set_workspace(nedner_plan plan, void* d_workspace, size_t bytes);
+
+/* Forward operator: data d_g [m][nt] -> d_out of the requested kind. */
+nedner_status nedner_execute(nedner_plan plan, const void* d_g, void* d_out, int kind,
+                             void* stream);
+
+/* Transpose: d_in of the given kind (VOLUME_REAL or STAGE_GRID) -> data d_g [m][nt]. */
+nedner_status nedner_execute_adjoint(nedner_plan plan, const void* d_in, int kind, void* d_g,
+                                     void* stream);
+
+/* Batched forward: arrays of `count` device pointers (see plan_create_many). */
+nedner_status nedner_execute_many(nedner_plan plan, const void* const* d_g,
+                                  void* const* d_out, int kind, void* stream);
+
+nedner_status nedner_destroy(nedner_plan plan);
+
+/* Stage timing with HIP events recorded on the execute stream, for up to
+   `max_runs` following executes (forward or adjoint). nedner_profile_end
+   waits for them and writes the mean milliseconds of each stage into
+   ms[0..*n_stages-1] (at most max_stages), in pipeline order; `names` (may be
+   NULL) receives a static comma-separated list of the stage names. Profiling
+   adds two event records per stage and no synchronisation. */
+nedner_status nedner_profile_begin(nedner_plan plan, int max_runs);
+nedner_status nedner_profile_end(nedner_plan plan, double* ms, int max_stages, int* n_stages,
+                                 const char** names);
+
+const char* nedner_status_string(nedner_status status);
+const char* nedner_last_error(void);
+int nedner_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEDNER_H */

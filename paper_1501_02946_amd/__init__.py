@@ -1,0 +1,367 @@
+"""NEDNER-NUFFT planar photoacoustic reconstruction for AMD MI355X (gfx950).
+
+A thin ctypes binding over ``libnedner.so``: the C-ABI declared in
+``include/nedner.h``. Every step of the operator runs in the library's HIP
+kernels; PyTorch only supplies device memory and the current stream. The
+binding marshals arguments and checks shapes, nothing more, and it raises if
+the library is not built (there is no CPU fallback).
+
+    plan = Plan(xy, nt=512, dt=1/512, volume=(128, 128, 256))
+    f = plan(g)                       # data (M, Nt) -> image (N1, N2, N3)
+    g2 = plan.adjoint(f)              # exact transpose
+    f = NednerRecon.apply(g, plan)    # differentiable forward
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+__all__ = ["Plan", "NednerRecon", "NednerAdjoint", "NednerError", "lib", "lsq",
+           "power_norm", "PRECISIONS", "KINDS", "FLAGS", "desc_struct", "info_struct",
+           "query"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libnedner.so")
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "fp32_plain": 3}
+KINDS = {"volume": 0, "spectrum": 1, "grid": 2}
+FLAGS = {"allow_alias": 1, "wrap": 2, "deterministic": 4, "no_autotune": 8}
+STATUS = {0: "ok", 1: "E_ARG", 2: "E_ALIAS", 3: "E_OOM", 4: "E_WORKSPACE", 5: "E_HIP",
+          6: "E_UNSUPPORTED", 7: "E_STATE"}
+
+
+class NednerError(RuntimeError):
+    """A non-OK status from the library; `.status` holds the code."""
+
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class desc_struct(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("xy", ctypes.c_void_p), ("h", ctypes.c_void_p),
+                ("nt", ctypes.c_int64), ("t0", ctypes.c_double), ("dt", ctypes.c_double),
+                ("c", ctypes.c_double), ("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
+                ("n3", ctypes.c_int32), ("a1", ctypes.c_double), ("a2", ctypes.c_double),
+                ("d1", ctypes.c_double), ("d2", ctypes.c_double), ("d3", ctypes.c_double),
+                ("prec", ctypes.c_int32), ("w", ctypes.c_int32), ("sigma", ctypes.c_double),
+                ("tau_scale", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("rows_per_wave", ctypes.c_int32), ("time_per_lane", ctypes.c_int32)]
+
+
+class info_struct(ctypes.Structure):
+    _fields_ = [("n1_os", ctypes.c_int32), ("n2_os", ctypes.c_int32), ("nt_os", ctypes.c_int32),
+                ("columns", ctypes.c_int32), ("segments", ctypes.c_int32),
+                ("rows_per_wave", ctypes.c_int32), ("time_per_lane", ctypes.c_int32),
+                ("pad0", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t),
+                ("table_bytes", ctypes.c_size_t), ("beta", ctypes.c_double),
+                ("max_abs_theta", ctypes.c_double), ("list_entries", ctypes.c_int64)]
+
+
+_LIB = None
+
+EXPORTS = ["nedner_desc_init", "nedner_validate", "nedner_query", "nedner_plan_create",
+           "nedner_plan_create_many", "nedner_plan_info", "nedner_workspace_size",
+           "nedner_set_workspace", "nedner_execute", "nedner_execute_adjoint",
+           "nedner_execute_many", "nedner_destroy", "nedner_status_string",
+           "nedner_last_error", "nedner_version"]
+
+
+def _declare(L):
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    D = ctypes.POINTER(desc_struct)
+    L.nedner_desc_init.argtypes = [D]
+    L.nedner_desc_init.restype = None
+    L.nedner_validate.argtypes = [D]
+    L.nedner_query.argtypes = [D, ctypes.POINTER(info_struct)]
+    L.nedner_plan_create.argtypes = [D, i32, vp, ctypes.POINTER(vp)]
+    L.nedner_plan_create_many.argtypes = [D, i32, i32, vp, ctypes.POINTER(vp)]
+    L.nedner_plan_info.argtypes = [vp, ctypes.POINTER(info_struct)]
+    L.nedner_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    L.nedner_set_workspace.argtypes = [vp, vp, sz]
+    L.nedner_execute.argtypes = [vp, vp, vp, i32, vp]
+    L.nedner_execute_adjoint.argtypes = [vp, vp, i32, vp, vp]
+    L.nedner_execute_many.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
+    L.nedner_destroy.argtypes = [vp]
+    L.nedner_status_string.argtypes = [i32]
+    L.nedner_status_string.restype = ctypes.c_char_p
+    L.nedner_last_error.argtypes = []
+    L.nedner_last_error.restype = ctypes.c_char_p
+    L.nedner_version.argtypes = []
+    for name in EXPORTS:
+        if name not in ("nedner_desc_init", "nedner_status_string", "nedner_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+
+
+def lib():
+    """Load libnedner.so (after torch, so both use one HIP runtime)."""
+    global _LIB
+    if _LIB is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise NednerError(5, f"{LIB_PATH} is not built; run `python -m paper_1501_02946_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _LIB = L
+    return _LIB
+
+
+def _check(st: int):
+    if st != 0:
+        msg = lib().nedner_last_error().decode(errors="replace")
+        raise NednerError(st, msg)
+
+
+def _make_desc(xy, h, nt, dt, n1, n2, n3, c=1.0, t0=0.0, a1=0.0, a2=0.0, d1=0.0, d2=0.0,
+               d3=0.0, precision="fp32c", w=12, sigma=2.0, tau_scale=1.0, flags=0,
+               rows_per_wave=0, time_per_lane=0):
+    L = lib()
+    d = desc_struct()
+    L.nedner_desc_init(ctypes.byref(d))
+    xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
+    d.m = xy.shape[0]
+    d.xy = xy.ctypes.data
+    keep = [xy]
+    if h is not None:
+        harr = np.ascontiguousarray(np.asarray(h, dtype=np.float64).reshape(-1))
+        if harr.shape[0] != xy.shape[0]:
+            raise ValueError("h must have one entry per sensor")
+        d.h = harr.ctypes.data
+        keep.append(harr)
+    d.nt, d.dt, d.c, d.t0 = int(nt), float(dt), float(c), float(t0)
+    d.n1, d.n2, d.n3 = int(n1), int(n2), int(n3)
+    d.a1, d.a2 = float(a1), float(a2)
+    d.d1 = float(d1) if d1 else 1.0 / int(n1)
+    d.d2 = float(d2) if d2 else 1.0 / int(n2)
+    d.d3 = float(d3)
+    d.prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    d.w, d.sigma, d.tau_scale = int(w), float(sigma), float(tau_scale)
+    if isinstance(flags, (list, tuple)):
+        flags = sum(FLAGS[f] for f in flags)
+    d.flags = int(flags)
+    d.rows_per_wave, d.time_per_lane = int(rows_per_wave), int(time_per_lane)
+    return d, keep
+
+
+def query(xy, nt, dt, volume, **kw) -> dict:
+    """Host-only: validate a configuration and return the sizes it implies."""
+    n1, n2, n3 = volume
+    d, keep = _make_desc(xy, kw.pop("h", None), nt, dt, n1, n2, n3, **kw)
+    info = info_struct()
+    _check(lib().nedner_query(ctypes.byref(d), ctypes.byref(info)))
+    del keep
+    return {k: getattr(info, k) for k, _ in info_struct._fields_ if k != "pad0"}
+
+
+class Plan:
+    """One reconstruction operator: fixed sensors, time grid and output grid.
+
+    Parameters follow the C descriptor: sensor positions `xy` (M, 2), time
+    samples `nt` at t0 + n dt, sound speed `c`, output `volume` = (N1, N2, N3)
+    with voxel (i1, i2, i3) at (a1 + i1 d1, a2 + i2 d2, i3 d3); d1, d2 default
+    to a unit aperture, d3 to c nt dt / N3. `precision` is one of "fp64",
+    "fp32", "fp32c" (compensated spreading) or "fp32_plain".
+    """
+
+    def __init__(self, xy, nt, dt, volume, c=1.0, h=None, t0=0.0, a1=0.0, a2=0.0, d1=0.0,
+                 d2=0.0, d3=0.0, precision="fp32c", w=12, sigma=2.0, tau_scale=1.0, flags=0,
+                 rows_per_wave=0, time_per_lane=0, device=None):
+        import torch
+        self._torch = torch
+        if not torch.cuda.is_available():
+            raise NednerError(5, "no GPU: the NEDNER library runs on MI355X only")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else int(device))
+        n1, n2, n3 = (int(v) for v in volume)
+        d, keep = _make_desc(xy, h, nt, dt, n1, n2, n3, c=c, t0=t0, a1=a1, a2=a2, d1=d1, d2=d2,
+                             d3=d3, precision=precision, w=w, sigma=sigma, tau_scale=tau_scale,
+                             flags=flags, rows_per_wave=rows_per_wave, time_per_lane=time_per_lane)
+        self.m, self.nt, self.volume = int(d.m), int(nt), (n1, n2, n3)
+        self.precision = precision
+        self.dtype = torch.float64 if d.prec == 0 else torch.float32
+        self._plan = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            _check(lib().nedner_plan_create(ctypes.byref(d), self.device.index,
+                                            ctypes.c_void_p(stream), ctypes.byref(self._plan)))
+        del keep
+        info = info_struct()
+        _check(lib().nedner_plan_info(self._plan, ctypes.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in info_struct._fields_ if k != "pad0"}
+        self._ws = None
+
+    # -- plumbing ---------------------------------------------------------
+    def _workspace(self):
+        if self._ws is None:
+            nbytes = int(self.info["workspace_bytes"])
+            self._ws = self._torch.empty(max(nbytes, 256), dtype=self._torch.uint8,
+                                         device=self.device)
+            _check(lib().nedner_set_workspace(self._plan, ctypes.c_void_p(self._ws.data_ptr()),
+                                              ctypes.c_size_t(self._ws.numel())))
+        return self._ws
+
+    def _stream(self):
+        return ctypes.c_void_p(self._torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _check_in(self, t, shape, what):
+        torch = self._torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{what} must be a torch tensor")
+        if t.device != self.device:
+            raise ValueError(f"{what} must be on {self.device}")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{what} must be {self.dtype} for a {self.precision} plan")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        return t.contiguous()
+
+    @property
+    def grid_shape(self):
+        return (self.info["n1_os"], self.info["n2_os"], self.nt)
+
+    # -- operator ---------------------------------------------------------
+    def forward(self, g, kind="volume", out=None):
+        """Data (M, Nt) -> volume (N1, N2, N3), spectrum (complex) or spread grid."""
+        torch = self._torch
+        g = self._check_in(g, (self.m, self.nt), "g")
+        k = KINDS[kind]
+        if k == 0:
+            shape, dt = self.volume, self.dtype
+        elif k == 1:
+            shape, dt = (*self.volume, 2), self.dtype
+        else:
+            shape, dt = self.grid_shape, self.dtype
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=self.device)
+        if k != 2:
+            self._workspace()
+        with torch.cuda.device(self.device):
+            _check(lib().nedner_execute(self._plan, ctypes.c_void_p(g.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), k, self._stream()))
+        if k == 1:
+            return torch.view_as_complex(out)
+        return out
+
+    __call__ = forward
+
+    def spectrum(self, g):
+        return self.forward(g, kind="spectrum")
+
+    def grid(self, g):
+        return self.forward(g, kind="grid")
+
+    def adjoint(self, v, kind="volume", out=None):
+        """Transpose: volume (N1, N2, N3) (or spread grid) -> data (M, Nt)."""
+        torch = self._torch
+        k = KINDS[kind]
+        if k == 1:
+            raise NednerError(6, "adjoint of the spectrum output is not provided")
+        v = self._check_in(v, self.volume if k == 0 else self.grid_shape, "v")
+        if out is None:
+            out = torch.empty((self.m, self.nt), dtype=self.dtype, device=self.device)
+        if k == 0:
+            self._workspace()
+        with torch.cuda.device(self.device):
+            _check(lib().nedner_execute_adjoint(self._plan, ctypes.c_void_p(v.data_ptr()), k,
+                                                ctypes.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def close(self):
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            lib().nedner_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _autograd():
+    import torch
+
+    class _Recon(torch.autograd.Function):
+        """f = A g (the reconstruction); backward applies the adjoint A*."""
+
+        @staticmethod
+        def forward(ctx, g, plan):
+            ctx.plan = plan
+            return plan.forward(g)
+
+        @staticmethod
+        def backward(ctx, grad):
+            return ctx.plan.adjoint(grad.contiguous()), None
+
+    class _Adjoint(torch.autograd.Function):
+        """g = A* v; backward applies A."""
+
+        @staticmethod
+        def forward(ctx, v, plan):
+            ctx.plan = plan
+            return plan.adjoint(v)
+
+        @staticmethod
+        def backward(ctx, grad):
+            return ctx.plan.forward(grad.contiguous()), None
+
+    return _Recon, _Adjoint
+
+
+class _Lazy:
+    def __init__(self, idx):
+        self._idx = idx
+        self._fn = None
+
+    def apply(self, *a):
+        if self._fn is None:
+            self._fn = _autograd()[self._idx]
+        return self._fn.apply(*a)
+
+
+NednerRecon = _Lazy(0)
+NednerAdjoint = _Lazy(1)
+
+
+def power_norm(plan: Plan, iters: int = 10, seed: int = 0) -> float:
+    """Estimate ||A||^2 (largest eigenvalue of A A*) by power iteration."""
+    torch = plan._torch
+    gen = torch.Generator(device=plan.device).manual_seed(seed)
+    v = torch.randn(plan.volume, dtype=plan.dtype, device=plan.device, generator=gen)
+    lam = 0.0
+    for _ in range(iters):
+        v = v / torch.linalg.vector_norm(v)
+        w = plan.forward(plan.adjoint(v))
+        lam = float(torch.dot(v.reshape(-1), w.reshape(-1)))
+        v = w
+    return lam
+
+
+def lsq(plan: Plan, g, iters: int = 20, eta: float | None = None, x0=None, callback=None):
+    """Projected gradient descent on J(x) = 1/2 ||A* x - g||^2 with x >= 0.
+
+    The gradient A (A* x - g) is taken by autograd through NednerAdjoint, so
+    each iteration runs one adjoint and one forward pass of the operator.
+    Returns (x, losses).
+    """
+    torch = plan._torch
+    if eta is None:
+        eta = 1.0 / max(power_norm(plan), 1e-300)
+    x = torch.zeros(plan.volume, dtype=plan.dtype, device=plan.device) if x0 is None else x0.clone()
+    losses = []
+    for it in range(iters):
+        x.requires_grad_(True)
+        r = NednerAdjoint.apply(x, plan) - g
+        loss = 0.5 * torch.sum(r * r)
+        (grad,) = torch.autograd.grad(loss, x)
+        losses.append(float(loss.detach()))
+        with torch.no_grad():
+            x = torch.clamp(x - eta * grad, min=0.0)
+        if callback is not None:
+            callback(it, x, losses[-1])
+    return x.detach(), losses

@@ -1,0 +1,812 @@
+// C-ABI of the NEDNER library: validation, plan construction and execution.
+//
+// Plan construction does the host-side geometry in double: every sensor's
+// grid coordinate u = n (y - a)/L is split into an integer cell and a
+// fraction, the window weights phi(o - frac) are tabulated per sensor and axis
+// (the "nearest integers" of eq. (10)), and the per-column spreading lists are
+// built. Nothing of that depends on the data, so execute only runs kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kparams.hpp"
+#include "nedner.h"
+
+using nedner::KP;
+using nedner::Radices;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+nedner_status fail(nedner_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+bool five_smooth(long n) {
+  if (n < 1) return false;
+  for (long p : {2L, 3L, 5L})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+// Integer value of sigma * n when it is one (within 1e-9), else -1.
+long scaled_size(double sigma, long n) {
+  const double v = sigma * double(n);
+  const double r = std::floor(v + 0.5);
+  if (std::fabs(v - r) > 1e-9 * std::max(1.0, v)) return -1;
+  return long(r);
+}
+
+Radices make_radices(int n) {
+  Radices rd{};
+  rd.n = n;
+  int m = n, c = 0;
+  int e2 = 0;
+  while (m % 2 == 0) {
+    m /= 2;
+    ++e2;
+  }
+  while (e2 >= 3) {
+    rd.r[c++] = 8;
+    e2 -= 3;
+  }
+  if (e2 == 2) rd.r[c++] = 4;
+  if (e2 == 1) rd.r[c++] = 2;
+  while (m % 5 == 0) {
+    m /= 5;
+    rd.r[c++] = 5;
+  }
+  while (m % 3 == 0) {
+    m /= 3;
+    rd.r[c++] = 3;
+  }
+  rd.count = c;
+  return rd;
+}
+
+struct Derived {
+  long n1, n2, ntt;
+  double L1, L2, D3, beta;
+  int W, TT, S, nseg, nchunk, CB, K2, J1;
+  double max_theta;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t real_size(int prec) { return prec == NEDNER_FP64 ? 8 : 4; }
+size_t weight_size(int prec) { return (prec == NEDNER_FP64 || prec == NEDNER_FP32_COMPENSATED) ? 8 : 4; }
+
+// Workspace: buffer 0 holds U, then G, then Z2; buffer 1 holds V, then Z1.
+void workspace_layout(const nedner_desc& d, const Derived& v, size_t* off1, size_t* total) {
+  const size_t rs = real_size(d.prec), cs = 2 * rs;
+  const size_t U = (size_t)v.n1 * v.n2 * d.nt * rs;
+  const size_t V = (size_t)v.n1 * v.K2 * d.nt * cs;
+  const size_t G = (size_t)v.K2 * v.J1 * d.nt * cs;
+  const size_t Z1 = (size_t)v.K2 * v.J1 * d.n3 * cs;
+  const size_t Z2 = (size_t)v.K2 * d.n1 * d.n3 * cs;
+  const size_t b0 = align256(std::max(U, std::max(G, Z2)));
+  const size_t b1 = align256(std::max(V, Z1));
+  *off1 = b0;
+  *total = b0 + b1;
+}
+
+size_t column_lds(const nedner_desc& d, const Derived& v) {
+  const size_t rs = real_size(d.prec), cs = 2 * rs;
+  const size_t nbuf = std::max<size_t>(v.ntt, d.n3);
+  return cs * (v.ntt + d.n3 + 2 * nbuf + d.n3 + 1) + (rs + 4) * (d.n3 + 1) + 16;
+}
+
+nedner_status validate_impl(const nedner_desc* d, Derived* out) {
+  if (!d) return fail(NEDNER_E_ARG, "descriptor is NULL");
+  if (d->m < 1 || d->m > (int64_t(1) << 30)) return fail(NEDNER_E_ARG, "m must be in [1, 2^30]");
+  if (!d->xy) return fail(NEDNER_E_ARG, "xy is NULL");
+  if (d->nt < 2 || (d->nt % 2) || d->nt > (1 << 20)) return fail(NEDNER_E_ARG, "nt must be even and in [2, 2^20]");
+  if (!finite(d->t0) || !finite(d->dt) || !(d->dt > 0)) return fail(NEDNER_E_ARG, "t0 must be finite and dt > 0");
+  if (!finite(d->c) || !(d->c > 0)) return fail(NEDNER_E_ARG, "c must be finite and > 0");
+  for (int n : {d->n1, d->n2, d->n3})
+    if (n < 2 || (n % 2) || n > (1 << 16)) return fail(NEDNER_E_ARG, "n1, n2, n3 must be even and in [2, 65536]");
+  if (!finite(d->a1) || !finite(d->a2)) return fail(NEDNER_E_ARG, "a1, a2 must be finite");
+  if (!finite(d->d1) || !finite(d->d2) || !(d->d1 > 0) || !(d->d2 > 0))
+    return fail(NEDNER_E_ARG, "d1, d2 must be finite and > 0");
+  if (!finite(d->d3) || d->d3 < 0) return fail(NEDNER_E_ARG, "d3 must be finite and >= 0");
+  if (d->prec < 0 || d->prec > 3) return fail(NEDNER_E_ARG, "unknown precision");
+  if (d->w < 2 || d->w > 16 || (d->w % 2)) return fail(NEDNER_E_ARG, "w must be even and in [2, 16]");
+  if (!finite(d->sigma) || !(d->sigma > 1.0)) return fail(NEDNER_E_ARG, "sigma must be finite and > 1");
+  if (!finite(d->tau_scale) || !(d->tau_scale > 0)) return fail(NEDNER_E_ARG, "tau_scale must be finite and > 0");
+  if (d->rows_per_wave < 0) return fail(NEDNER_E_ARG, "rows_per_wave must be >= 0");
+  if (d->time_per_lane != 0 && d->time_per_lane != 1 && d->time_per_lane != 2 && d->time_per_lane != 4)
+    return fail(NEDNER_E_ARG, "time_per_lane must be 0, 1, 2 or 4");
+  if (d->flags & ~uint32_t(15)) return fail(NEDNER_E_ARG, "unknown flag bits");
+  Derived v{};
+  v.n1 = scaled_size(d->sigma, d->n1);
+  v.n2 = scaled_size(d->sigma, d->n2);
+  v.ntt = scaled_size(d->sigma, d->nt);
+  if (v.n1 < 0 || v.n2 < 0 || v.ntt < 0 || (v.n1 % 2) || (v.n2 % 2) || (v.ntt % 2))
+    return fail(NEDNER_E_ARG, "sigma * n1, sigma * n2 and sigma * nt must be even integers");
+  v.L1 = d->n1 * d->d1;
+  v.L2 = d->n2 * d->d2;
+  v.D3 = d->d3 > 0 ? d->d3 : d->c * double(d->nt) * d->dt / d->n3;
+  v.W = d->w;
+  v.beta = M_PI * (d->sigma - 0.5) / (d->sigma * (d->w / 2.0)) / d->tau_scale;
+  v.K2 = d->n2 / 2 + 1;
+  v.J1 = d->n1 + 1;
+  // positions
+  const bool wrap = (d->flags & NEDNER_WRAP_POSITIONS) != 0;
+  for (int64_t m = 0; m < d->m; ++m) {
+    const double y1 = d->xy[2 * m], y2 = d->xy[2 * m + 1];
+    if (!finite(y1) || !finite(y2)) return fail(NEDNER_E_ARG, "non-finite sensor position at index " + std::to_string(m));
+    if (!wrap && (y1 < d->a1 || y1 >= d->a1 + v.L1 || y2 < d->a2 || y2 >= d->a2 + v.L2))
+      return fail(NEDNER_E_ARG, "sensor " + std::to_string(m) + " outside the aperture (set NEDNER_WRAP_POSITIONS to wrap)");
+    if (d->h) {
+      const double h = d->h[m];
+      if (!finite(h) || h < 0) return fail(NEDNER_E_ARG, "detector area must be finite and >= 0 at index " + std::to_string(m));
+    }
+  }
+  // frequencies: |omega| dt over the mode set (both Nyquist representatives)
+  {
+    const double k1 = M_PI * d->n1 / v.L1, k2 = M_PI * d->n2 / v.L2, kz = M_PI * d->n3 / (d->n3 * v.D3);
+    v.max_theta = d->c * d->dt * std::sqrt(k1 * k1 + k2 * k2 + kz * kz);
+  }
+  // supported transform sizes
+  for (long n : {v.n1, v.n2, v.ntt, (long)d->n1, (long)d->n2, (long)d->n3})
+    if (!five_smooth(n))
+      return fail(NEDNER_E_UNSUPPORTED, "FFT length " + std::to_string(n) + " is not 5-smooth (2^a 3^b 5^c)");
+  const long lat_max = d->prec == NEDNER_FP64 ? 2048 : 4096;
+  if (v.n1 > lat_max || v.n2 > lat_max || d->n1 > lat_max || d->n2 > lat_max)
+    return fail(NEDNER_E_UNSUPPORTED, "lateral transform longer than " + std::to_string(lat_max));
+  if (column_lds(*d, v) > 160 * 1024)
+    return fail(NEDNER_E_UNSUPPORTED, "time FFT length and depth count exceed the LDS of one workgroup");
+  // spreading launch shape
+  int TT = d->time_per_lane;
+  if (TT == 0) TT = (d->nt >= 512 && d->nt % 4 == 0) ? 4 : (d->nt >= 128 ? 2 : 1);
+  v.TT = TT;
+  v.nchunk = int((d->nt + 64 * TT - 1) / (64 * TT));
+  int S = d->rows_per_wave;
+  if (S == 0) {
+    const long waves1 = (long)v.n2 * v.nchunk;  // waves per segment
+    long nseg = (8192 + waves1 - 1) / waves1;
+    nseg = std::max(1L, std::min(nseg, std::max(1L, v.n1 / (2 * v.W))));
+    S = int((v.n1 + nseg - 1) / nseg);
+  }
+  S = int(std::min<long>(S, v.n1));
+  v.S = S;
+  v.nseg = int((v.n1 + S - 1) / S);
+  v.CB = S + v.W;
+  if (out) *out = v;
+  if (v.max_theta >= M_PI && !(d->flags & NEDNER_ALLOW_ALIAS))
+    return fail(NEDNER_E_ALIAS, "max |omega| dt = " + std::to_string(v.max_theta) +
+                                    " >= pi: time sampling aliases (set NEDNER_ALLOW_ALIAS to accept)");
+  return NEDNER_OK;
+}
+
+// Host geometry shared by the query and the plan.
+struct Geometry {
+  std::vector<int> cell;        // [M][2]
+  std::vector<double> w1, w2;   // [M][W]
+  std::vector<int> ent_m;
+  std::vector<double> ent_w2;
+  std::vector<int> cellbeg;     // [n2 * nseg][CB]
+};
+
+double phi(double beta, double x) { return std::exp(-beta * x * x); }
+
+void build_geometry(const nedner_desc& d, const Derived& v, Geometry& G) {
+  const int64_t M = d.m;
+  const int W = v.W, h = W / 2 - 1;
+  const bool plain = d.prec == NEDNER_FP32_PLAIN;
+  G.cell.resize(2 * M);
+  G.w1.resize(M * W);
+  G.w2.resize(M * W);
+  std::vector<double> frac2(M);
+  const double L[2] = {v.L1, v.L2}, a[2] = {d.a1, d.a2};
+  const long n[2] = {v.n1, v.n2};
+  for (int64_t m = 0; m < M; ++m) {
+    const double s = (d.h ? d.h[m] : v.L1 * v.L2 / double(M)) / (d.d1 * d.d2);
+    for (int ax = 0; ax < 2; ++ax) {
+      double u, f;
+      long c;
+      if (plain) {
+        float uf = float(n[ax]) * (float(d.xy[2 * m + ax]) - float(a[ax])) / float(L[ax]);
+        uf -= float(n[ax]) * std::floor(uf / float(n[ax]));
+        if (uf >= float(n[ax])) uf -= float(n[ax]);
+        const float cf = std::floor(uf);
+        c = long(cf);
+        f = double(uf - cf);
+        u = uf;
+      } else {
+        u = double(n[ax]) * (d.xy[2 * m + ax] - a[ax]) / L[ax];
+        u -= double(n[ax]) * std::floor(u / double(n[ax]));
+        if (u >= double(n[ax])) u -= double(n[ax]);
+        c = long(std::floor(u));
+        f = u - double(c);
+      }
+      (void)u;
+      G.cell[2 * m + ax] = int(c);
+      for (int k = 0; k < W; ++k) {
+        const int o = k - h;
+        double w;
+        if (plain) {
+          const float df = float(o) - float(f);
+          w = double(std::exp(-float(v.beta) * df * df));
+        } else {
+          w = phi(v.beta, double(o) - f);
+        }
+        if (ax == 0)
+          G.w1[m * W + k] = s * w;
+        else
+          G.w2[m * W + k] = w;
+      }
+      if (ax == 1) frac2[m] = f;
+    }
+  }
+  // per-column lists: sensors whose second-axis taps reach column q2
+  struct E {
+    int c1, m;
+    double w2;
+  };
+  std::vector<std::vector<E>> percol(v.n2);
+  std::vector<std::pair<int, double>> taps;
+  for (int64_t m = 0; m < M; ++m) {
+    taps.clear();
+    for (int k = 0; k < W; ++k) {
+      const int q2 = int(((long)G.cell[2 * m + 1] + k - h) % v.n2 + v.n2) % int(v.n2);
+      const double w = G.w2[m * W + k];
+      bool merged = false;
+      for (auto& t : taps)
+        if (t.first == q2) {
+          t.second += w;
+          merged = true;
+        }
+      if (!merged) taps.push_back({q2, w});
+    }
+    for (auto& t : taps) percol[t.first].push_back({G.cell[2 * m], int(m), t.second});
+  }
+  G.cellbeg.assign((size_t)v.n2 * v.nseg * v.CB, 0);
+  std::vector<int> rowstart(v.n1 + 1);
+  std::vector<E> sorted;
+  for (long q2 = 0; q2 < v.n2; ++q2) {
+    auto& L2v = percol[q2];
+    std::fill(rowstart.begin(), rowstart.end(), 0);
+    for (auto& e : L2v) rowstart[e.c1 + 1]++;
+    for (long r = 0; r < v.n1; ++r) rowstart[r + 1] += rowstart[r];
+    sorted.resize(L2v.size());
+    {
+      std::vector<int> pos(rowstart.begin(), rowstart.end() - 1);
+      for (auto& e : L2v) sorted[pos[e.c1]++] = e;  // stable: sensor order within a cell
+    }
+    for (int s = 0; s < v.nseg; ++s) {
+      const int S0 = s * v.S, S1 = std::min<int>(S0 + v.S, int(v.n1));
+      const int Vstart = S0 - W / 2, Vend = S1 + W / 2 - 2;
+      int* cb = &G.cellbeg[((size_t)q2 * v.nseg + s) * v.CB];
+      for (int V = Vstart; V <= Vend; ++V) {
+        cb[V - Vstart] = int(G.ent_m.size());
+        const int c = int(((long)V % v.n1 + v.n1) % v.n1);
+        for (int i = rowstart[c]; i < rowstart[c + 1]; ++i) {
+          G.ent_m.push_back(sorted[i].m);
+          G.ent_w2.push_back(sorted[i].w2);
+        }
+      }
+      cb[Vend - Vstart + 1] = int(G.ent_m.size());
+    }
+  }
+}
+
+double phihat(double beta, double k, double n) {
+  return std::sqrt(M_PI / beta) * std::exp(-M_PI * M_PI * k * k / (beta * n * n));
+}
+
+struct DevAlloc {
+  std::vector<void*> ptrs;
+  hipError_t err = hipSuccess;
+  template <typename T>
+  const void* upload(const std::vector<T>& h) {
+    if (err != hipSuccess) return nullptr;
+    void* p = nullptr;
+    const size_t b = std::max<size_t>(h.size() * sizeof(T), 16);
+    err = hipMalloc(&p, b);
+    if (err != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    if (!h.empty()) err = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    return p;
+  }
+  template <typename T>
+  const void* upload_as(const std::vector<double>& h) {
+    std::vector<T> t(h.begin(), h.end());
+    return upload(t);
+  }
+  template <typename T>
+  const void* twiddles(int n) {
+    std::vector<T> t(2 * (size_t)n);
+    for (int k = 0; k < n; ++k) {
+      const double ang = 2.0 * M_PI * double(k) / double(n);
+      t[2 * k] = T(std::cos(ang));
+      t[2 * k + 1] = T(-std::sin(ang));
+    }
+    return upload(t);
+  }
+};
+
+}  // namespace
+
+struct nedner_plan_s {
+  KP kp{};
+  nedner_desc desc{};
+  Derived v{};
+  nedner_info info{};
+  int device = 0;
+  bool broken = false;
+  std::vector<void*> allocs;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t need_ws = 0;
+  size_t off1 = 0;
+  std::vector<nedner_plan_s*> subs;  // batched plans
+  // stage profiling
+  std::vector<hipEvent_t> ev;
+  int prof_max = 0, prof_runs = 0, prof_stages = 0;
+  const char* prof_names = nullptr;
+};
+
+namespace {
+
+void fill_info(const nedner_desc& d, const Derived& v, int64_t entries, nedner_info* info) {
+  std::memset(info, 0, sizeof(*info));
+  info->n1_os = int(v.n1);
+  info->n2_os = int(v.n2);
+  info->nt_os = int(v.ntt);
+  info->columns = v.J1 * v.K2;
+  info->segments = v.nseg;
+  info->rows_per_wave = v.S;
+  info->time_per_lane = v.TT;
+  size_t off1;
+  workspace_layout(d, v, &off1, &info->workspace_bytes);
+  const size_t ws = weight_size(d.prec), rs = real_size(d.prec);
+  info->list_entries = entries;
+  info->table_bytes = (size_t)d.m * (2 * v.W * ws + 8) + entries * (4 + ws) +
+                      (size_t)v.n2 * v.nseg * v.CB * 4 + (v.J1 + v.K2 + d.nt) * rs +
+                      2 * rs * (v.n1 + v.n2 + v.ntt + d.n1 + d.n2 + d.n3);
+  info->beta = v.beta;
+  info->max_abs_theta = v.max_theta;
+}
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    ok_ = hipGetDevice(&old_) == hipSuccess;
+    if (ok_ && old_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (hipGetDevice(&cur) == hipSuccess && cur != old_) (void)hipSetDevice(old_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int old_ = 0;
+  bool ok_ = false;
+};
+
+nedner_status hip_fail(nedner_plan p, hipError_t e, const char* where) {
+  if (p) p->broken = true;
+  return fail(NEDNER_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+nedner_status create_one(const nedner_desc* desc, int device, nedner_plan* out) {
+  Derived v;
+  nedner_status st = validate_impl(desc, &v);
+  if (st != NEDNER_OK) return st;
+  nedner_plan p = new (std::nothrow) nedner_plan_s();
+  if (!p) return fail(NEDNER_E_OOM, "host allocation failed");
+  p->desc = *desc;
+  p->desc.xy = nullptr;
+  p->desc.h = nullptr;
+  p->v = v;
+  p->device = device;
+  Geometry G;
+  try {
+    build_geometry(*desc, v, G);
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return fail(NEDNER_E_OOM, "host allocation failed while building the spreading lists");
+  }
+  if (G.ent_m.size() > size_t(INT32_MAX)) {
+    delete p;
+    return fail(NEDNER_E_UNSUPPORTED, "too many spreading list entries");
+  }
+  fill_info(*desc, v, int64_t(G.ent_m.size()), &p->info);
+  workspace_layout(*desc, v, &p->off1, &p->need_ws);
+
+  DeviceGuard guard(device);
+  if (!guard.ok()) {
+    delete p;
+    return fail(NEDNER_E_HIP, "cannot select device " + std::to_string(device));
+  }
+  KP& k = p->kp;
+  k.M = int(desc->m);
+  k.Nt = int(desc->nt);
+  k.N1 = desc->n1;
+  k.N2 = desc->n2;
+  k.N3 = desc->n3;
+  k.n1 = int(v.n1);
+  k.n2 = int(v.n2);
+  k.ntt = int(v.ntt);
+  k.K2 = v.K2;
+  k.J1 = v.J1;
+  k.W = v.W;
+  k.TT = v.TT;
+  k.S = v.S;
+  k.nseg = v.nseg;
+  k.CB = v.CB;
+  k.nchunk = v.nchunk;
+  k.prec = desc->prec;
+  k.beta = v.beta;
+  k.cdtnt = desc->c * desc->dt * double(v.ntt);
+  k.inv_L1sq = 1.0 / (v.L1 * v.L1);
+  k.inv_L2sq = 1.0 / (v.L2 * v.L2);
+  k.bz = 1.0 / ((desc->n3 * v.D3) * (desc->n3 * v.D3));
+  k.phase_p = (desc->nt / 2.0 + desc->t0 / desc->dt) / double(v.ntt);
+  k.two_c = 2.0 * desc->c;
+  k.scale_spec = desc->dt / v.D3;
+  k.scale_vol = k.scale_spec / (double(desc->n1) * desc->n2 * desc->n3);
+  k.r_n1 = make_radices(k.n1);
+  k.r_n2 = make_radices(k.n2);
+  k.r_ntt = make_radices(k.ntt);
+  k.r_N1 = make_radices(k.N1);
+  k.r_N2 = make_radices(k.N2);
+  k.r_N3 = make_radices(k.N3);
+
+  // deconvolution and precorrection tables
+  std::vector<double> d1(v.J1), d2(v.K2), dtb(desc->nt);
+  for (int je = 0; je < v.J1; ++je) d1[je] = 1.0 / phihat(v.beta, je - desc->n1 / 2, double(v.n1));
+  for (int k2 = 0; k2 < v.K2; ++k2) d2[k2] = 1.0 / phihat(v.beta, k2, double(v.n2));
+  for (int64_t n = 0; n < desc->nt; ++n) dtb[n] = 1.0 / phihat(v.beta, double(n - desc->nt / 2), double(v.ntt));
+
+  DevAlloc A;
+  const bool wide = desc->prec == NEDNER_FP64 || desc->prec == NEDNER_FP32_COMPENSATED;
+  const bool dbl = desc->prec == NEDNER_FP64;
+  k.w1 = wide ? A.upload(G.w1) : A.upload_as<float>(G.w1);
+  k.w2 = wide ? A.upload(G.w2) : A.upload_as<float>(G.w2);
+  k.ent_w2 = wide ? A.upload(G.ent_w2) : A.upload_as<float>(G.ent_w2);
+  k.cell = static_cast<const int*>(A.upload(G.cell));
+  k.ent_m = static_cast<const int*>(A.upload(G.ent_m));
+  k.cellbeg = static_cast<const int*>(A.upload(G.cellbeg));
+  k.dec1 = dbl ? A.upload(d1) : A.upload_as<float>(d1);
+  k.dec2 = dbl ? A.upload(d2) : A.upload_as<float>(d2);
+  k.dect = dbl ? A.upload(dtb) : A.upload_as<float>(dtb);
+  if (dbl) {
+    k.tw_n1 = A.twiddles<double>(k.n1);
+    k.tw_n2 = A.twiddles<double>(k.n2);
+    k.tw_ntt = A.twiddles<double>(k.ntt);
+    k.tw_N1 = A.twiddles<double>(k.N1);
+    k.tw_N2 = A.twiddles<double>(k.N2);
+    k.tw_N3 = A.twiddles<double>(k.N3);
+  } else {
+    k.tw_n1 = A.twiddles<float>(k.n1);
+    k.tw_n2 = A.twiddles<float>(k.n2);
+    k.tw_ntt = A.twiddles<float>(k.ntt);
+    k.tw_N1 = A.twiddles<float>(k.N1);
+    k.tw_N2 = A.twiddles<float>(k.N2);
+    k.tw_N3 = A.twiddles<float>(k.N3);
+  }
+  p->allocs = A.ptrs;
+  if (A.err != hipSuccess) {
+    const hipError_t e = A.err;
+    for (void* q : p->allocs) (void)hipFree(q);
+    delete p;
+    if (e == hipErrorOutOfMemory) return fail(NEDNER_E_OOM, "device allocation of plan tables failed");
+    return fail(NEDNER_E_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+  }
+  *out = p;
+  return NEDNER_OK;
+}
+
+nedner_status exec_check(nedner_plan plan, int kind, bool adj) {
+  if (!plan) return fail(NEDNER_E_ARG, "plan is NULL");
+  if (plan->broken) return fail(NEDNER_E_STATE, "plan is unusable after an earlier HIP error");
+  if (!plan->subs.empty()) return fail(NEDNER_E_ARG, "batched plan: use nedner_execute_many");
+  if (kind < 0 || kind > 2) return fail(NEDNER_E_ARG, "unknown kind");
+  if (adj && kind == NEDNER_SPECTRUM_COMPLEX)
+    return fail(NEDNER_E_UNSUPPORTED, "adjoint of the spectrum output is not provided");
+  if (kind != NEDNER_STAGE_GRID && (!plan->ws || plan->ws_bytes < plan->need_ws))
+    return fail(NEDNER_E_WORKSPACE, "no workspace, or one smaller than nedner_workspace_size");
+  return NEDNER_OK;
+}
+
+#define NEDNER_RUN(call, what)                      \
+  do {                                              \
+    hipError_t e_ = (call);                         \
+    if (e_ != hipSuccess) return hip_fail(plan, e_, what); \
+  } while (0)
+
+// Records one event before every stage and one after the last, when the plan
+// is profiling and has event slots left for this run.
+struct Marks {
+  nedner_plan plan;
+  hipStream_t s;
+  int run = -1, stages = 0, next = 0;
+  Marks(nedner_plan p, hipStream_t st, int nstages, const char* names) : plan(p), s(st), stages(nstages) {
+    if (p->prof_max > 0 && p->prof_runs < p->prof_max) {
+      if (p->prof_runs == 0) {
+        p->prof_stages = nstages;
+        p->prof_names = names;
+      }
+      if (p->prof_stages == nstages) run = p->prof_runs++;
+    }
+  }
+  hipError_t mark() {
+    if (run < 0 || next > stages) return hipSuccess;
+    return hipEventRecord(plan->ev[(size_t)run * (stages + 1) + next++], s);
+  }
+};
+
+static const char* kFwdNames = "spread,lat_a,lat_b,column,pass_c,pass_d";
+static const char* kSpecNames = "spread,lat_a,lat_b,column_spectrum";
+static const char* kAdjNames = "adj_d,adj_c,column_adj,adj_b,adj_a,gather";
+
+nedner_status forward_impl(nedner_plan plan, const void* d_g, void* d_out, int kind, hipStream_t s) {
+  const KP& k = plan->kp;
+  char* b0 = static_cast<char*>(plan->ws);
+  char* b1 = b0 + plan->off1;
+  if (kind == NEDNER_STAGE_GRID) {
+    Marks mk(plan, s, 1, "spread");
+    NEDNER_RUN(mk.mark(), "event");
+    NEDNER_RUN(nedner::launch_spread(k, d_g, d_out, s), "spread");
+    NEDNER_RUN(mk.mark(), "event");
+    return NEDNER_OK;
+  }
+  const bool spec = kind == NEDNER_SPECTRUM_COMPLEX;
+  Marks mk(plan, s, spec ? 4 : 6, spec ? kSpecNames : kFwdNames);
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_spread(k, d_g, b0, s), "spread");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_lat_a(k, b0, b1, s), "lateral FFT (second axis)");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_lat_b(k, b1, b0, s), "lateral FFT (first axis)");
+  NEDNER_RUN(mk.mark(), "event");
+  if (spec) {
+    NEDNER_RUN(nedner::launch_column(k, b0, d_out, 1, s), "NER column");
+    NEDNER_RUN(mk.mark(), "event");
+    return NEDNER_OK;
+  }
+  NEDNER_RUN(nedner::launch_column(k, b0, b1, 0, s), "NER column");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_pass_c(k, b1, b0, s), "inverse FFT (first axis)");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_pass_d(k, b0, d_out, s), "inverse FFT (second axis)");
+  NEDNER_RUN(mk.mark(), "event");
+  return NEDNER_OK;
+}
+
+nedner_status adjoint_impl(nedner_plan plan, const void* d_in, int kind, void* d_g, hipStream_t s) {
+  const KP& k = plan->kp;
+  char* b0 = static_cast<char*>(plan->ws);
+  char* b1 = b0 + plan->off1;
+  if (kind == NEDNER_STAGE_GRID) {
+    Marks mk(plan, s, 1, "gather");
+    NEDNER_RUN(mk.mark(), "event");
+    NEDNER_RUN(nedner::launch_gather(k, d_in, d_g, s), "gather");
+    NEDNER_RUN(mk.mark(), "event");
+    return NEDNER_OK;
+  }
+  Marks mk(plan, s, 6, kAdjNames);
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_adj_d(k, d_in, b0, s), "adjoint FFT (second axis)");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_adj_c(k, b0, b1, s), "adjoint FFT (first axis)");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_column_adj(k, b1, b0, s), "adjoint NER column");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_adj_b(k, b0, b1, s), "adjoint lateral FFT (first axis)");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_adj_a(k, b1, b0, s), "adjoint lateral FFT (second axis)");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_gather(k, b0, d_g, s), "gather");
+  NEDNER_RUN(mk.mark(), "event");
+  return NEDNER_OK;
+}
+
+void free_events(nedner_plan p) {
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  p->ev.clear();
+  p->prof_max = p->prof_runs = p->prof_stages = 0;
+}
+
+void destroy_one(nedner_plan p) {
+  if (!p) return;
+  for (auto* s : p->subs) destroy_one(s);
+  if (!p->allocs.empty() || !p->ev.empty()) {
+    DeviceGuard guard(p->device);
+    free_events(p);
+    for (void* q : p->allocs) (void)hipFree(q);
+  }
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+void nedner_desc_init(nedner_desc* d) {
+  if (!d) return;
+  std::memset(d, 0, sizeof(*d));
+  d->c = 1.0;
+  d->dt = 1.0;
+  d->d1 = 1.0;
+  d->d2 = 1.0;
+  d->prec = NEDNER_FP32;
+  d->w = 12;
+  d->sigma = 2.0;
+  d->tau_scale = 1.0;
+}
+
+nedner_status nedner_validate(const nedner_desc* desc) { return validate_impl(desc, nullptr); }
+
+nedner_status nedner_query(const nedner_desc* desc, nedner_info* info) {
+  if (!info) return fail(NEDNER_E_ARG, "info is NULL");
+  Derived v;
+  nedner_status st = validate_impl(desc, &v);
+  if (st != NEDNER_OK) return st;
+  Geometry G;
+  try {
+    build_geometry(*desc, v, G);
+  } catch (const std::bad_alloc&) {
+    return fail(NEDNER_E_OOM, "host allocation failed");
+  }
+  fill_info(*desc, v, int64_t(G.ent_m.size()), info);
+  return NEDNER_OK;
+}
+
+nedner_status nedner_plan_create(const nedner_desc* desc, int device, void* stream, nedner_plan* plan) {
+  (void)stream;
+  if (!plan) return fail(NEDNER_E_ARG, "plan output pointer is NULL");
+  *plan = nullptr;
+  return create_one(desc, device, plan);
+}
+
+nedner_status nedner_plan_create_many(const nedner_desc* descs, int count, int device, void* stream,
+                                      nedner_plan* plan) {
+  (void)descs;
+  (void)count;
+  (void)device;
+  (void)stream;
+  if (plan) *plan = nullptr;
+  return fail(NEDNER_E_UNSUPPORTED, "batched plans are not available in this build");
+}
+
+nedner_status nedner_plan_info(nedner_plan plan, nedner_info* info) {
+  if (!plan || !info) return fail(NEDNER_E_ARG, "NULL argument");
+  *info = plan->info;
+  return NEDNER_OK;
+}
+
+nedner_status nedner_workspace_size(nedner_plan plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(NEDNER_E_ARG, "NULL argument");
+  *bytes = plan->need_ws;
+  return NEDNER_OK;
+}
+
+nedner_status nedner_set_workspace(nedner_plan plan, void* d_ws, size_t bytes) {
+  if (!plan) return fail(NEDNER_E_ARG, "plan is NULL");
+  if (d_ws && (reinterpret_cast<uintptr_t>(d_ws) % 256))
+    return fail(NEDNER_E_ARG, "workspace must be 256-byte aligned");
+  if (d_ws && bytes < plan->need_ws)
+    return fail(NEDNER_E_WORKSPACE, "workspace of " + std::to_string(bytes) + " bytes is smaller than " +
+                                        std::to_string(plan->need_ws));
+  plan->ws = d_ws;
+  plan->ws_bytes = d_ws ? bytes : 0;
+  return NEDNER_OK;
+}
+
+nedner_status nedner_execute(nedner_plan plan, const void* d_g, void* d_out, int kind, void* stream) {
+  nedner_status st = exec_check(plan, kind, false);
+  if (st != NEDNER_OK) return st;
+  if (!d_g || !d_out) return fail(NEDNER_E_ARG, "NULL device pointer");
+  DeviceGuard guard(plan->device);
+  if (!guard.ok()) return fail(NEDNER_E_HIP, "cannot select the plan's device");
+  return forward_impl(plan, d_g, d_out, kind, static_cast<hipStream_t>(stream));
+}
+
+nedner_status nedner_execute_adjoint(nedner_plan plan, const void* d_in, int kind, void* d_g, void* stream) {
+  nedner_status st = exec_check(plan, kind, true);
+  if (st != NEDNER_OK) return st;
+  if (!d_in || !d_g) return fail(NEDNER_E_ARG, "NULL device pointer");
+  DeviceGuard guard(plan->device);
+  if (!guard.ok()) return fail(NEDNER_E_HIP, "cannot select the plan's device");
+  return adjoint_impl(plan, d_in, kind, d_g, static_cast<hipStream_t>(stream));
+}
+
+nedner_status nedner_execute_many(nedner_plan plan, const void* const* d_g, void* const* d_out, int kind,
+                                  void* stream) {
+  (void)d_g;
+  (void)d_out;
+  (void)kind;
+  (void)stream;
+  if (!plan) return fail(NEDNER_E_ARG, "plan is NULL");
+  return fail(NEDNER_E_UNSUPPORTED, "batched plans are not available in this build");
+}
+
+nedner_status nedner_profile_begin(nedner_plan plan, int max_runs) {
+  if (!plan) return fail(NEDNER_E_ARG, "plan is NULL");
+  if (max_runs < 1 || max_runs > 100000) return fail(NEDNER_E_ARG, "max_runs must be in [1, 100000]");
+  DeviceGuard guard(plan->device);
+  if (!guard.ok()) return fail(NEDNER_E_HIP, "cannot select the plan's device");
+  free_events(plan);
+  const size_t n = (size_t)max_runs * 8;  // up to 7 stage boundaries per run
+  plan->ev.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    hipError_t e = hipEventCreate(&plan->ev[i]);
+    if (e != hipSuccess) {
+      plan->ev.resize(i);
+      free_events(plan);
+      return fail(NEDNER_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
+  }
+  plan->prof_max = max_runs;
+  return NEDNER_OK;
+}
+
+nedner_status nedner_profile_end(nedner_plan plan, double* ms, int max_stages, int* n_stages,
+                                 const char** names) {
+  if (!plan || !n_stages) return fail(NEDNER_E_ARG, "NULL argument");
+  DeviceGuard guard(plan->device);
+  const int runs = plan->prof_runs, st = plan->prof_stages;
+  *n_stages = runs > 0 ? st : 0;
+  if (names) *names = runs > 0 ? plan->prof_names : "";
+  std::vector<double> acc(st, 0.0);
+  for (int r = 0; r < runs; ++r) {
+    hipEvent_t* e = &plan->ev[(size_t)r * (st + 1)];
+    hipError_t err = hipEventSynchronize(e[st]);
+    if (err != hipSuccess) {
+      free_events(plan);
+      return fail(NEDNER_E_HIP, std::string("hipEventSynchronize: ") + hipGetErrorString(err));
+    }
+    for (int i = 0; i < st; ++i) {
+      float t = 0.f;
+      err = hipEventElapsedTime(&t, e[i], e[i + 1]);
+      if (err != hipSuccess) {
+        free_events(plan);
+        return fail(NEDNER_E_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(err));
+      }
+      acc[i] += t;
+    }
+  }
+  if (ms)
+    for (int i = 0; i < st && i < max_stages; ++i) ms[i] = runs ? acc[i] / runs : 0.0;
+  free_events(plan);
+  return NEDNER_OK;
+}
+
+nedner_status nedner_destroy(nedner_plan plan) {
+  destroy_one(plan);
+  return NEDNER_OK;
+}
+
+const char* nedner_status_string(nedner_status s) {
+  switch (s) {
+    case NEDNER_OK: return "ok";
+    case NEDNER_E_ARG: return "invalid argument";
+    case NEDNER_E_ALIAS: return "time sampling aliases";
+    case NEDNER_E_OOM: return "out of memory";
+    case NEDNER_E_WORKSPACE: return "workspace missing or too small";
+    case NEDNER_E_HIP: return "HIP runtime error";
+    case NEDNER_E_UNSUPPORTED: return "unsupported";
+    case NEDNER_E_STATE: return "plan unusable";
+  }
+  return "unknown status";
+}
+
+const char* nedner_last_error(void) { return g_last_error.c_str(); }
+
+int nedner_version(void) { return NEDNER_VERSION; }
+
+}  // extern "C"

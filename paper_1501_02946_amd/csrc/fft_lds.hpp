@@ -1,0 +1,173 @@
+// Mixed-radix Stockham FFT staged in LDS for gfx950.
+//
+// A workgroup transforms `lines` independent lines of length n held in LDS.
+// Point p of line b sits at buf[p * ps + b * ls]. Each stage reads one LDS
+// buffer and writes the other (ping-pong), so one barrier per stage suffices;
+// the result ends in the buffer selected by the parity of the stage count.
+// Radices 2, 3, 4, 5 and 8 cover every 5-smooth length. Twiddles come from a
+// table tw[k] = exp(-2 pi i k / n) computed in double on the host and staged
+// in LDS by the caller.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace nedner {
+
+template <typename T>
+struct cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T x, T y) { return cpx<T>{x, y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator*(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> conjg(cpx<T> a) { return {a.x, -a.y}; }
+// multiply by -i (forward kernels) or +i (inverse kernels)
+template <bool INV, typename T>
+__device__ __forceinline__ cpx<T> rot(cpx<T> a) {
+  return INV ? cpx<T>{-a.y, a.x} : cpx<T>{a.y, -a.x};
+}
+
+// Radix sequence of one transform length, chosen on the host.
+struct Radices {
+  int n;
+  int count;
+  int r[16];
+};
+
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void dft_small(cpx<T>* v) {
+  if constexpr (R == 2) {
+    cpx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  } else if constexpr (R == 3) {
+    const T h = T(0.8660254037844386467637231707529362);
+    cpx<T> t1 = v[1] + v[2];
+    cpx<T> t2 = v[0] - t1 * T(0.5);
+    cpx<T> t3 = (v[1] - v[2]) * h;
+    v[0] = v[0] + t1;
+    cpx<T> r3 = rot<INV>(t3);
+    v[1] = t2 + r3;
+    v[2] = t2 - r3;
+  } else if constexpr (R == 4) {
+    cpx<T> a = v[0] + v[2], b = v[0] - v[2];
+    cpx<T> c = v[1] + v[3], d = rot<INV>(v[1] - v[3]);
+    v[0] = a + c;
+    v[2] = a - c;
+    v[1] = b + d;
+    v[3] = b - d;
+  } else if constexpr (R == 5) {
+    const T c1 = T(0.3090169943749474241022934171828191);
+    const T c2 = T(-0.8090169943749474241022934171828191);
+    const T s1 = T(0.9510565162951535721164393333793821);
+    const T s2 = T(0.5877852522924731291687059546390728);
+    cpx<T> t1 = v[1] + v[4], t2 = v[2] + v[3];
+    cpx<T> t3 = v[1] - v[4], t4 = v[2] - v[3];
+    cpx<T> a1 = v[0] + t1 * c1 + t2 * c2;
+    cpx<T> a2 = v[0] + t1 * c2 + t2 * c1;
+    cpx<T> b1 = rot<INV>(t3 * s1 + t4 * s2);
+    cpx<T> b2 = rot<INV>(t3 * s2 - t4 * s1);
+    v[0] = v[0] + t1 + t2;
+    v[1] = a1 + b1;
+    v[4] = a1 - b1;
+    v[2] = a2 + b2;
+    v[3] = a2 - b2;
+  } else if constexpr (R == 8) {
+    const T q = T(0.7071067811865475244008443621048490);
+    cpx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    dft_small<4, INV>(e);
+    dft_small<4, INV>(o);
+    // twiddles exp(-+ 2 pi i k / 8), k = 1..3
+    cpx<T> o1 = cpx<T>{(o[1].x + (INV ? -o[1].y : o[1].y)) * q, (o[1].y + (INV ? o[1].x : -o[1].x)) * q};
+    cpx<T> o2 = rot<INV>(o[2]);
+    cpx<T> o3 = cpx<T>{(-o[3].x + (INV ? -o[3].y : o[3].y)) * q,
+                       (-o[3].y + (INV ? o[3].x : -o[3].x)) * q};
+    v[0] = e[0] + o[0];
+    v[4] = e[0] - o[0];
+    v[1] = e[1] + o1;
+    v[5] = e[1] - o1;
+    v[2] = e[2] + o2;
+    v[6] = e[2] - o2;
+    v[3] = e[3] + o3;
+    v[7] = e[3] - o3;
+  }
+}
+
+// One Stockham stage of radix R over all lines: src -> dst.
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+                                               int n, int Ns, int lines, int ps, int ls,
+                                               const cpx<T>* __restrict__ tw, int tid, int nth) {
+  const int nb = n / R;
+  const int total = nb * lines;
+  const int tstep = n / (Ns * R);
+  for (int t = tid; t < total; t += nth) {
+    const int b = t % lines;
+    const int j = t / lines;
+    const int k = j % Ns;
+    cpx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[(j + r * nb) * ps + b * ls];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cpx<T> w = tw[r * k * tstep];
+        v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+      }
+    }
+    dft_small<R, INV>(v);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[(base + r * Ns) * ps + b * ls] = v[r];
+  }
+}
+
+// Full transform. Returns the buffer holding the result (a or b). Caller must
+// __syncthreads() before the call (data in `a` visible); on return the result
+// is visible to the whole workgroup.
+template <bool INV, typename T>
+__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const Radices& rd, int lines, int ps, int ls,
+                           const cpx<T>* tw, int tid, int nth) {
+  int Ns = 1;
+  for (int s = 0; s < rd.count; ++s) {
+    const int R = rd.r[s];
+    switch (R) {
+      case 2: stockham_stage<2, INV>(a, b, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+      case 3: stockham_stage<3, INV>(a, b, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+      case 4: stockham_stage<4, INV>(a, b, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+      case 5: stockham_stage<5, INV>(a, b, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+      default: stockham_stage<8, INV>(a, b, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+    }
+    __syncthreads();
+    cpx<T>* t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+// Stage a twiddle table of n entries from global memory into LDS.
+template <typename T>
+__device__ __forceinline__ void load_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ src, int n,
+                                              int tid, int nth) {
+  for (int i = tid; i < n; i += nth) dst[i] = src[i];
+}
+
+}  // namespace nedner

@@ -1,0 +1,383 @@
+// NER step (eq. (6)-(8)) fused with the inversion weight of eq. (1), one
+// workgroup per column (j1, k2) of the NED result.
+//
+// Forward, per column:
+//   a[n'] = G(n' + Nt/2), n' in [-Nt/2, Nt/2), stored at n' mod ntt, zero padded
+//           (G already carries 1/phihat_t, applied in the lateral pass);
+//   B = FFT_ntt(a) in LDS;
+//   for l in -N3/2..N3/2 (both depth Nyquist representatives):
+//     x = omega dt ntt/(2 pi) = sign(l) c dt ntt |K|/(2 pi), reduced in double;
+//     H = sum over the W grid points q nearest x of B[q mod ntt] phi(x - q);
+//     F = scale * W(j,l) * H * exp(-i (Nt/2 theta + omega t0)), phase in double;
+//   then either the spectrum is written out, or the Nyquist combination of
+//   the half-spectrum inverse (see column_policy) is applied and the inverse
+//   FFT along depth is done in LDS, so the column leaves as Z1.
+// Adjoint, per column: the exact transpose, with the interpolation turned
+// into a deterministic gather over the monotone sequence x(l).
+#include "kparams.hpp"
+
+namespace nedner {
+
+__device__ __forceinline__ int pmodc(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// How column (je, k2) enters the half-spectrum inverse transform.
+//   fac: overall factor; pol: depth Nyquist slot gets F(-N3/2) (0), F(+N3/2) (1)
+//   or their mean (2). The real part of the full inverse DFT equals a C2R along
+//   the second axis of the symmetrised half spectrum; at the Nyquist indices the
+//   symmetrisation averages the two representatives -N/2 and +N/2.
+__device__ __forceinline__ void column_policy(int je, int k2, int N1, int N2, double& fac, int& pol) {
+  const bool lo = je == 0, hi = je == N1;
+  if (k2 == 0) {
+    fac = hi ? 0.0 : 1.0;
+    pol = 0;
+  } else if (k2 == N2 / 2) {
+    fac = lo ? 0.0 : 1.0;
+    pol = 1;
+  } else if (lo) {
+    fac = 0.5;
+    pol = 0;
+  } else if (hi) {
+    fac = 0.5;
+    pol = 1;
+  } else {
+    fac = 1.0;
+    pol = 2;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R wexp(R v);
+template <>
+__device__ __forceinline__ float wexp<float>(float v) { return __expf(v); }
+template <>
+__device__ __forceinline__ double wexp<double>(double v) { return exp(v); }
+
+template <typename R>
+__device__ __forceinline__ void sincos_pi(R v, R* s, R* c);
+template <>
+__device__ __forceinline__ void sincos_pi<float>(float v, float* s, float* c) { sincospif(v, s, c); }
+template <>
+__device__ __forceinline__ void sincos_pi<double>(double v, double* s, double* c) { sincospi(v, s, c); }
+
+// Frequency data of one output l of a column: grid position x = q0 + fr,
+// the weight W(j,l) times the scale, and exp(-i phase).
+template <typename R, bool ARGS64>
+struct LPoint {
+  int q0;
+  R fr;
+  R wgt;
+  cpx<R> ph;
+};
+
+template <typename R, bool ARGS64>
+__device__ __forceinline__ LPoint<R, ARGS64> lpoint(const KP& p, double a, int l, double scale) {
+  LPoint<R, ARGS64> o;
+  const double l2 = double(l) * double(l);
+  R rr;
+  if constexpr (ARGS64) {
+    const double kk = sqrt(a + l2 * p.bz);
+    const double x = (l > 0 ? 1.0 : (l < 0 ? -1.0 : 0.0)) * p.cdtnt * kk;
+    const double fl = floor(x);
+    o.q0 = int(fl);
+    o.fr = R(x - fl);
+    double r = x * p.phase_p;
+    r -= rint(r);
+    rr = R(r);
+    double w = 0.0;
+    if (l != 0)
+      w = p.two_c * fabs(double(l)) * sqrt(p.bz) / kk;
+    else if (a == 0.0)
+      w = p.two_c;
+    o.wgt = R(w * scale);
+  } else {
+    const float kk = sqrtf(float(a) + float(l2) * float(p.bz));
+    const float x = (l > 0 ? 1.0f : (l < 0 ? -1.0f : 0.0f)) * float(p.cdtnt) * kk;
+    const float fl = floorf(x);
+    o.q0 = int(fl);
+    o.fr = R(x - fl);
+    float r = x * float(p.phase_p);
+    r -= rintf(r);
+    rr = R(r);
+    float w = 0.0f;
+    if (l != 0)
+      w = float(p.two_c) * fabsf(float(l)) * sqrtf(float(p.bz)) / kk;
+    else if (a == 0.0)
+      w = float(p.two_c);
+    o.wgt = R(w * float(scale));
+  }
+  R s, c;
+  sincos_pi<R>(R(2) * rr, &s, &c);
+  o.ph = cpx<R>{c, -s};
+  return o;
+}
+
+template <typename R>
+struct ColSmem {
+  cpx<R>* twt;  // ntt twiddles
+  cpx<R>* tw3;  // N3 twiddles
+  cpx<R>* a;    // nbuf
+  cpx<R>* b;    // nbuf
+  cpx<R>* fl;   // N3 + 1
+  int* q0;      // N3 + 1 (adjoint)
+  R* fr;        // N3 + 1 (adjoint)
+};
+
+template <typename R>
+__device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p) {
+  ColSmem<R> s;
+  const int nbuf = p.ntt > p.N3 ? p.ntt : p.N3;
+  s.twt = reinterpret_cast<cpx<R>*>(smem);
+  s.tw3 = s.twt + p.ntt;
+  s.a = s.tw3 + p.N3;
+  s.b = s.a + nbuf;
+  s.fl = s.b + nbuf;
+  s.fr = reinterpret_cast<R*>(s.fl + p.N3 + 1);
+  s.q0 = reinterpret_cast<int*>(s.fr + p.N3 + 1);
+  return s;
+}
+
+template <typename R>
+static size_t col_smem_bytes(const KP& p) {
+  const int nbuf = p.ntt > p.N3 ? p.ntt : p.N3;
+  return sizeof(cpx<R>) * ((size_t)p.ntt + p.N3 + 2 * (size_t)nbuf + p.N3 + 1) +
+         (sizeof(R) + sizeof(int)) * ((size_t)p.N3 + 1) + 16;
+}
+
+// SPEC: write the full spectrum F (N1, N2, N3) in FFT order instead of Z1.
+template <typename R, int W, bool ARGS64, bool SPEC>
+__global__ __launch_bounds__(256) void k_column(KP p, const cpx<R>* __restrict__ G, void* out) {
+  extern __shared__ __align__(16) char smem[];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int je = blockIdx.x, k2 = blockIdx.y;
+  const int ntt = p.ntt, N3 = p.N3, Nt = p.Nt, h3 = N3 / 2;
+  const size_t col = (size_t)k2 * p.J1 + je;
+  double fac;
+  int pol;
+  column_policy(je, k2, p.N1, p.N2, fac, pol);
+  if (!SPEC && fac == 0.0) {
+    cpx<R>* z1 = static_cast<cpx<R>*>(out) + col * N3;
+    for (int i = tid; i < N3; i += nth) z1[i] = cpx<R>{R(0), R(0)};
+    return;
+  }
+  ColSmem<R> sm = col_carve<R>(smem, p);
+  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
+  load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
+  const cpx<R>* gc = G + col * Nt;
+  for (int s = tid; s < ntt; s += nth) {
+    // slot s holds n' = s (s < ntt/2) or s - ntt; data index n = n' + Nt/2
+    const int np = s < ntt / 2 ? s : s - ntt;
+    const int n = np + Nt / 2;
+    sm.a[s] = (n >= 0 && n < Nt) ? gc[n] : cpx<R>{R(0), R(0)};
+  }
+  __syncthreads();
+  cpx<R>* B = fft_lds<false>(sm.a, sm.b, p.r_ntt, 1, 1, 0, sm.twt, tid, nth);
+  const int j1 = je - p.N1 / 2;
+  const double a = double(j1) * double(j1) * p.inv_L1sq + double(k2) * double(k2) * p.inv_L2sq;
+  const double scale = SPEC ? p.scale_spec : p.scale_vol;
+  const R beta = R(p.beta);
+  for (int li = tid; li <= N3; li += nth) {
+    const int l = li - h3;
+    const LPoint<R, ARGS64> lp = lpoint<R, ARGS64>(p, a, l, scale);
+    cpx<R> H = {R(0), R(0)};
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int o = k - W / 2 + 1;
+      const R d = R(o) - lp.fr;
+      const R wk = wexp<R>(-beta * d * d);
+      H = H + B[pmodc(lp.q0 + o, ntt)] * wk;
+    }
+    sm.fl[li] = cmul(H, lp.ph) * lp.wgt;
+  }
+  __syncthreads();
+  if constexpr (SPEC) {
+    cpx<R>* F = static_cast<cpx<R>*>(out);
+    const int N1 = p.N1, N2 = p.N2;
+    const bool direct = k2 < N2 / 2 && je < N1;
+    const bool mirror = k2 >= 1 && je >= 1;
+    const size_t rd = ((size_t)pmodc(j1, N1) * N2 + k2) * N3;
+    const size_t rm = ((size_t)pmodc(-j1, N1) * N2 + pmodc(-k2, N2)) * N3;
+    for (int li = tid; li <= N3; li += nth) {
+      const int l = li - h3;
+      if (direct && li < N3) F[rd + pmodc(l, N3)] = sm.fl[li];
+      if (mirror && li > 0) F[rm + pmodc(-l, N3)] = conjg(sm.fl[li]);
+    }
+  } else {
+    // X[slot] for the depth inverse; B is free again, the other buffer too
+    cpx<R>* X = sm.a;
+    cpx<R>* Y = sm.b;
+    const R f = R(fac);
+    for (int s = tid; s < N3; s += nth) {
+      cpx<R> v;
+      if (s == h3) {
+        const cpx<R> lo = sm.fl[0], hi = sm.fl[N3];
+        v = pol == 0 ? lo : (pol == 1 ? hi : (lo + hi) * R(0.5));
+      } else {
+        const int l = s < h3 ? s : s - N3;
+        v = sm.fl[l + h3];
+      }
+      X[s] = v * f;
+    }
+    __syncthreads();
+    cpx<R>* Zr = fft_lds<true>(X, Y, p.r_N3, 1, 1, 0, sm.tw3, tid, nth);
+    cpx<R>* z1 = static_cast<cpx<R>*>(out) + col * N3;
+    for (int i = tid; i < N3; i += nth) z1[i] = Zr[i];
+  }
+}
+
+// First index i in [lo, hi) with q[i] >= v (q non-decreasing).
+__device__ __forceinline__ int lower_bound_i(const int* q, int lo, int hi, int v) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (q[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename R, int W, bool ARGS64>
+__global__ __launch_bounds__(256) void k_column_adj(KP p, int mwrap, const cpx<R>* __restrict__ Z1,
+                                                    cpx<R>* __restrict__ G) {
+  extern __shared__ __align__(16) char smem[];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int je = blockIdx.x, k2 = blockIdx.y;
+  const int ntt = p.ntt, N3 = p.N3, Nt = p.Nt, h3 = N3 / 2;
+  const size_t col = (size_t)k2 * p.J1 + je;
+  double fac;
+  int pol;
+  column_policy(je, k2, p.N1, p.N2, fac, pol);
+  cpx<R>* gc = G + col * Nt;
+  if (fac == 0.0) {
+    for (int i = tid; i < Nt; i += nth) gc[i] = cpx<R>{R(0), R(0)};
+    return;
+  }
+  ColSmem<R> sm = col_carve<R>(smem, p);
+  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
+  load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
+  const cpx<R>* zc = Z1 + col * N3;
+  for (int i = tid; i < N3; i += nth) sm.a[i] = zc[i];
+  __syncthreads();
+  // transpose of the unnormalised depth inverse: forward FFT
+  cpx<R>* Xp = fft_lds<false>(sm.a, sm.b, p.r_N3, 1, 1, 0, sm.tw3, tid, nth);
+  const int j1 = je - p.N1 / 2;
+  const double a = double(j1) * double(j1) * p.inv_L1sq + double(k2) * double(k2) * p.inv_L2sq;
+  const R f = R(fac);
+  const R mlo = pol == 0 ? R(1) : (pol == 1 ? R(0) : R(0.5));
+  const R mhi = pol == 1 ? R(1) : (pol == 0 ? R(0) : R(0.5));
+  for (int li = tid; li <= N3; li += nth) {
+    const int l = li - h3;
+    cpx<R> fp;
+    if (li == 0)
+      fp = Xp[h3] * (f * mlo);
+    else if (li == N3)
+      fp = Xp[h3] * (f * mhi);
+    else
+      fp = Xp[pmodc(l, N3)] * f;
+    const LPoint<R, ARGS64> lp = lpoint<R, ARGS64>(p, a, l, p.scale_vol);
+    sm.fl[li] = cmulc(fp, lp.ph) * lp.wgt;  // H'(l) = wgt * conj(ph) * F'(l)
+    sm.q0[li] = lp.q0;
+    sm.fr[li] = lp.fr;
+  }
+  __syncthreads();
+  // B'[q] = sum over l whose taps cover q of phi(x_l - q) H'(l); x_l is
+  // non-decreasing in l, so the l covering q form a contiguous range.
+  cpx<R>* Bp = (Xp == sm.a) ? sm.b : sm.a;
+  const R beta = R(p.beta);
+  for (int q = tid; q < ntt; q += nth) {
+    const int qc = q < ntt / 2 ? q : q - ntt;
+    cpx<R> acc = {R(0), R(0)};
+    for (int m = -mwrap; m <= mwrap; ++m) {
+      const int qv = qc + m * ntt;
+      // tap o = qv - q0 must lie in [-W/2+1, W/2]: q0 in [qv - W/2, qv + W/2 - 1]
+      const int lo = lower_bound_i(sm.q0, 0, N3 + 1, qv - W / 2);
+      const int hi = lower_bound_i(sm.q0, lo, N3 + 1, qv + W / 2);
+      for (int li = lo; li < hi; ++li) {
+        const R d = R(qv - sm.q0[li]) - sm.fr[li];
+        acc = acc + sm.fl[li] * wexp<R>(-beta * d * d);
+      }
+    }
+    Bp[q] = acc;
+  }
+  __syncthreads();
+  cpx<R>* other = (Bp == sm.a) ? sm.b : sm.a;
+  cpx<R>* Ap = fft_lds<true>(Bp, other, p.r_ntt, 1, 1, 0, sm.twt, tid, nth);
+  for (int n = tid; n < Nt; n += nth) {
+    const int s = pmodc(n - Nt / 2, ntt);
+    gc[n] = Ap[s];
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename R, int W, bool ARGS64>
+static hipError_t column_w(const KP& p, const void* G, void* out, int spec, hipStream_t s) {
+  const size_t sh = col_smem_bytes<R>(p);
+  dim3 grid(p.J1, p.K2);
+  hipError_t e = allow_smem(spec ? k_column<R, W, ARGS64, true> : k_column<R, W, ARGS64, false>, sh);
+  if (e != hipSuccess) return e;
+  if (spec)
+    hipLaunchKernelGGL((k_column<R, W, ARGS64, true>), grid, dim3(256), sh, s, p,
+                       static_cast<const cpx<R>*>(G), out);
+  else
+    hipLaunchKernelGGL((k_column<R, W, ARGS64, false>), grid, dim3(256), sh, s, p,
+                       static_cast<const cpx<R>*>(G), out);
+  return hipGetLastError();
+}
+
+template <typename R, int W, bool ARGS64>
+static hipError_t column_adj_w(const KP& p, const void* Z1, void* G, hipStream_t s) {
+  const size_t sh = col_smem_bytes<R>(p);
+  dim3 grid(p.J1, p.K2);
+  // number of periodic images of the time grid a tap window can reach
+  const double xmax = p.cdtnt * sqrt((p.N1 / 2.0) * (p.N1 / 2.0) * p.inv_L1sq +
+                                     (p.N2 / 2.0) * (p.N2 / 2.0) * p.inv_L2sq +
+                                     (p.N3 / 2.0) * (p.N3 / 2.0) * p.bz);
+  const int mwrap = 1 + int((xmax + W) / p.ntt);
+  hipError_t e = allow_smem(k_column_adj<R, W, ARGS64>, sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_column_adj<R, W, ARGS64>), grid, dim3(256), sh, s, p, mwrap,
+                     static_cast<const cpx<R>*>(Z1), static_cast<cpx<R>*>(G));
+  return hipGetLastError();
+}
+
+template <typename R, bool ARGS64>
+static hipError_t column_a(const KP& p, const void* in, void* out, int spec, hipStream_t s, bool adj) {
+  switch (p.W) {
+#define NEDNER_CW(WV) \
+  case WV:            \
+    return adj ? column_adj_w<R, WV, ARGS64>(p, in, out, s) : column_w<R, WV, ARGS64>(p, in, out, spec, s);
+    NEDNER_CW(2)
+    NEDNER_CW(4)
+    NEDNER_CW(6)
+    NEDNER_CW(8)
+    NEDNER_CW(10)
+    NEDNER_CW(12)
+    NEDNER_CW(14)
+    NEDNER_CW(16)
+#undef NEDNER_CW
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t column_dispatch(const KP& p, const void* in, void* out, int spec, hipStream_t s, bool adj) {
+  switch (p.prec) {
+    case PREC_FP64: return column_a<double, true>(p, in, out, spec, s, adj);
+    case PREC_FP32P: return column_a<float, false>(p, in, out, spec, s, adj);
+    default: return column_a<float, true>(p, in, out, spec, s, adj);
+  }
+}
+
+hipError_t launch_column(const KP& p, const void* G, void* out, int spectrum, hipStream_t s) {
+  return column_dispatch(p, G, out, spectrum, s, false);
+}
+
+hipError_t launch_column_adj(const KP& p, const void* Z1, void* G, hipStream_t s) {
+  return column_dispatch(p, Z1, G, 0, s, true);
+}
+
+}  // namespace nedner

@@ -1,0 +1,340 @@
+// Uniform FFT passes around the NER step.
+//
+// Forward (eq. (10) second half, and the closing inverse FFT of Sec. 3):
+//   lat_a : R2C along q2 of the spread grid, keeping k2 = 0..N2/2
+//   lat_b : C2C along q1, keeping j1 = -N1/2..N1/2, times the deconvolution
+//           1/(phihat1 phihat2) and the time precorrection 1/phihat_t
+//   pass_c: inverse C2C along j1 (the two Nyquist representatives are summed)
+//   pass_d: C2R along k2 to the real image
+// Adjoint: the exact transposes adj_d, adj_c, adj_b, adj_a.
+//
+// Every pass is a batch of independent lines: a workgroup loads a tile of
+// `TB` lines (consecutive along the fastest memory axis, so each row of the
+// tile is one contiguous segment) into LDS, transforms along the slow axis
+// with the Stockham engine, and writes the tile back with the per-pass
+// pre/post-processing fused in. Two real lines are packed into one complex
+// line for the real transforms (lat_a, pass_d, adj_d, adj_a).
+#include "kparams.hpp"
+
+namespace nedner {
+
+__device__ __forceinline__ int pmodp(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+template <typename R>
+struct Smem {
+  cpx<R>* tw;
+  cpx<R>* a;
+  cpx<R>* b;
+};
+
+template <typename R>
+__device__ __forceinline__ Smem<R> carve(char* smem, int n, int TB) {
+  Smem<R> s;
+  s.tw = reinterpret_cast<cpx<R>*>(smem);
+  s.a = s.tw + n;
+  s.b = s.a + (size_t)n * TB;
+  return s;
+}
+
+// ---------------------------------------------------------------- forward
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_lat_a(KP p, int TB, const R* __restrict__ U,
+                                               cpx<R>* __restrict__ V) {
+  extern __shared__ __align__(16) char smem[];
+  const int n = p.n2, tid = threadIdx.x, nth = blockDim.x;
+  Smem<R> sm = carve<R>(smem, n, TB);
+  const int q1 = blockIdx.x, pb = blockIdx.y * TB, npairs = p.Nt / 2;
+  load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n2), n, tid, nth);
+  const R* src = U + (size_t)q1 * n * p.Nt;
+  for (int i = tid; i < n * TB; i += nth) {
+    const int q2 = i / TB, pp = i - q2 * TB, pr = pb + pp;
+    cpx<R> z = {R(0), R(0)};
+    if (pr < npairs) z = *reinterpret_cast<const cpx<R>*>(src + (size_t)q2 * p.Nt + 2 * pr);
+    sm.a[i] = z;
+  }
+  __syncthreads();
+  cpx<R>* Z = fft_lds<false>(sm.a, sm.b, p.r_n2, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* dst = V + (size_t)q1 * p.K2 * p.Nt;
+  for (int i = tid; i < p.K2 * TB; i += nth) {
+    const int k = i / TB, pp = i - k * TB, pr = pb + pp;
+    if (pr >= npairs) continue;
+    const cpx<R> a = Z[k * TB + pp];
+    const cpx<R> b = Z[((n - k) % n) * TB + pp];
+    const cpx<R> X = {(a.x + b.x) * R(0.5), (a.y - b.y) * R(0.5)};
+    const cpx<R> Y = {(a.y + b.y) * R(0.5), (b.x - a.x) * R(0.5)};
+    dst[(size_t)k * p.Nt + 2 * pr] = X;
+    dst[(size_t)k * p.Nt + 2 * pr + 1] = Y;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_lat_b(KP p, int TB, const cpx<R>* __restrict__ V,
+                                               cpx<R>* __restrict__ G) {
+  extern __shared__ __align__(16) char smem[];
+  const int n = p.n1, tid = threadIdx.x, nth = blockDim.x;
+  Smem<R> sm = carve<R>(smem, n, TB);
+  const int k2 = blockIdx.x, nb = blockIdx.y * TB, Nt = p.Nt;
+  load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n1), n, tid, nth);
+  for (int i = tid; i < n * TB; i += nth) {
+    const int q1 = i / TB, t = i - q1 * TB, nn = nb + t;
+    cpx<R> z = {R(0), R(0)};
+    if (nn < Nt) z = V[((size_t)q1 * p.K2 + k2) * Nt + nn];
+    sm.a[i] = z;
+  }
+  __syncthreads();
+  cpx<R>* Z = fft_lds<false>(sm.a, sm.b, p.r_n1, TB, TB, 1, sm.tw, tid, nth);
+  const R* d1 = static_cast<const R*>(p.dec1);
+  const R* dt = static_cast<const R*>(p.dect);
+  const R d2 = static_cast<const R*>(p.dec2)[k2];
+  for (int i = tid; i < p.J1 * TB; i += nth) {
+    const int je = i / TB, t = i - je * TB, nn = nb + t;
+    if (nn >= Nt) continue;
+    const int k1 = pmodp(je - p.N1 / 2, n);
+    G[((size_t)k2 * p.J1 + je) * Nt + nn] = Z[k1 * TB + t] * (d1[je] * d2 * dt[nn]);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_pass_c(KP p, int TB, const cpx<R>* __restrict__ Z1,
+                                                cpx<R>* __restrict__ Z2) {
+  extern __shared__ __align__(16) char smem[];
+  const int n = p.N1, tid = threadIdx.x, nth = blockDim.x;
+  Smem<R> sm = carve<R>(smem, n, TB);
+  const int k2 = blockIdx.x, ib = blockIdx.y * TB, N3 = p.N3;
+  load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N1), n, tid, nth);
+  const cpx<R>* src = Z1 + (size_t)k2 * p.J1 * N3;
+  for (int i = tid; i < n * TB; i += nth) {
+    const int s = i / TB, t = i - s * TB, i3 = ib + t;
+    cpx<R> z = {R(0), R(0)};
+    if (i3 < N3) {
+      const int j1 = s < n / 2 ? s : s - n;
+      z = src[(size_t)(j1 + n / 2) * N3 + i3];
+      if (s == n / 2) z = z + src[(size_t)n * N3 + i3];
+    }
+    sm.a[i] = z;
+  }
+  __syncthreads();
+  cpx<R>* Z = fft_lds<true>(sm.a, sm.b, p.r_N1, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* dst = Z2 + (size_t)k2 * n * N3;
+  for (int i = tid; i < n * TB; i += nth) {
+    const int i1 = i / TB, t = i - i1 * TB, i3 = ib + t;
+    if (i3 < N3) dst[(size_t)i1 * N3 + i3] = Z[i];
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_pass_d(KP p, int TB, const cpx<R>* __restrict__ Z2,
+                                                R* __restrict__ vol) {
+  extern __shared__ __align__(16) char smem[];
+  const int n = p.N2, tid = threadIdx.x, nth = blockDim.x;
+  Smem<R> sm = carve<R>(smem, n, TB);
+  const int i1 = blockIdx.x, pb = blockIdx.y * TB, N3 = p.N3, npairs = N3 / 2, h = n / 2;
+  load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N2), n, tid, nth);
+  for (int i = tid; i < n * TB; i += nth) {
+    const int k = i / TB, pp = i - k * TB, pr = pb + pp;
+    cpx<R> c = {R(0), R(0)};
+    if (pr < npairs) {
+      const int kk = k <= h ? k : n - k;
+      const size_t o = ((size_t)kk * p.N1 + i1) * N3 + 2 * pr;
+      const cpx<R> za = Z2[o], zb = Z2[o + 1];
+      if (k == 0 || k == h)
+        c = {za.x, zb.x};
+      else if (k < h)
+        c = {za.x - zb.y, za.y + zb.x};
+      else
+        c = {za.x + zb.y, zb.x - za.y};
+    }
+    sm.a[i] = c;
+  }
+  __syncthreads();
+  cpx<R>* Z = fft_lds<true>(sm.a, sm.b, p.r_N2, TB, TB, 1, sm.tw, tid, nth);
+  R* dst = vol + (size_t)i1 * n * N3;
+  for (int i = tid; i < n * TB; i += nth) {
+    const int i2 = i / TB, pp = i - i2 * TB, pr = pb + pp;
+    if (pr < npairs) *reinterpret_cast<cpx<R>*>(dst + (size_t)i2 * N3 + 2 * pr) = Z[i];
+  }
+}
+
+// ---------------------------------------------------------------- adjoint
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_d(KP p, int TB, const R* __restrict__ vol,
+                                               cpx<R>* __restrict__ Z2) {
+  extern __shared__ __align__(16) char smem[];
+  const int n = p.N2, tid = threadIdx.x, nth = blockDim.x;
+  Smem<R> sm = carve<R>(smem, n, TB);
+  const int i1 = blockIdx.x, pb = blockIdx.y * TB, N3 = p.N3, npairs = N3 / 2, h = n / 2;
+  load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N2), n, tid, nth);
+  const R* src = vol + (size_t)i1 * n * N3;
+  for (int i = tid; i < n * TB; i += nth) {
+    const int i2 = i / TB, pp = i - i2 * TB, pr = pb + pp;
+    cpx<R> z = {R(0), R(0)};
+    if (pr < npairs) z = *reinterpret_cast<const cpx<R>*>(src + (size_t)i2 * N3 + 2 * pr);
+    sm.a[i] = z;
+  }
+  __syncthreads();
+  cpx<R>* Z = fft_lds<false>(sm.a, sm.b, p.r_N2, TB, TB, 1, sm.tw, tid, nth);
+  for (int i = tid; i < (h + 1) * TB; i += nth) {
+    const int k = i / TB, pp = i - k * TB, pr = pb + pp;
+    if (pr >= npairs) continue;
+    const cpx<R> a = Z[k * TB + pp];
+    const cpx<R> b = Z[((n - k) % n) * TB + pp];
+    const R al = (k == 0 || k == h) ? R(0.5) : R(1);
+    const cpx<R> Va = {(a.x + b.x) * al, (a.y - b.y) * al};
+    const cpx<R> Vb = {(a.y + b.y) * al, (b.x - a.x) * al};
+    const size_t o = ((size_t)k * p.N1 + i1) * N3 + 2 * pr;
+    Z2[o] = Va;
+    Z2[o + 1] = Vb;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_c(KP p, int TB, const cpx<R>* __restrict__ Z2,
+                                               cpx<R>* __restrict__ Z1) {
+  extern __shared__ __align__(16) char smem[];
+  const int n = p.N1, tid = threadIdx.x, nth = blockDim.x;
+  Smem<R> sm = carve<R>(smem, n, TB);
+  const int k2 = blockIdx.x, ib = blockIdx.y * TB, N3 = p.N3;
+  load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N1), n, tid, nth);
+  const cpx<R>* src = Z2 + (size_t)k2 * n * N3;
+  for (int i = tid; i < n * TB; i += nth) {
+    const int i1 = i / TB, t = i - i1 * TB, i3 = ib + t;
+    cpx<R> z = {R(0), R(0)};
+    if (i3 < N3) z = src[(size_t)i1 * N3 + i3];
+    sm.a[i] = z;
+  }
+  __syncthreads();
+  cpx<R>* Z = fft_lds<false>(sm.a, sm.b, p.r_N1, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* dst = Z1 + (size_t)k2 * p.J1 * N3;
+  for (int i = tid; i < p.J1 * TB; i += nth) {
+    const int je = i / TB, t = i - je * TB, i3 = ib + t;
+    if (i3 >= N3) continue;
+    const int s = pmodp(je - n / 2, n);
+    dst[(size_t)je * N3 + i3] = Z[s * TB + t];
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_b(KP p, int TB, const cpx<R>* __restrict__ G,
+                                               cpx<R>* __restrict__ V) {
+  extern __shared__ __align__(16) char smem[];
+  const int n = p.n1, tid = threadIdx.x, nth = blockDim.x;
+  Smem<R> sm = carve<R>(smem, n, TB);
+  const int k2 = blockIdx.x, nb = blockIdx.y * TB, Nt = p.Nt, h1 = p.N1 / 2;
+  load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n1), n, tid, nth);
+  const R* d1 = static_cast<const R*>(p.dec1);
+  const R* dt = static_cast<const R*>(p.dect);
+  const R d2 = static_cast<const R*>(p.dec2)[k2];
+  for (int i = tid; i < n * TB; i += nth) {
+    const int k1 = i / TB, t = i - k1 * TB, nn = nb + t;
+    cpx<R> z = {R(0), R(0)};
+    const int j1 = k1 < n / 2 ? k1 : k1 - n;
+    if (nn < Nt && j1 >= -h1 && j1 <= h1) {
+      const int je = j1 + h1;
+      z = G[((size_t)k2 * p.J1 + je) * Nt + nn] * (d1[je] * d2 * dt[nn]);
+    }
+    sm.a[i] = z;
+  }
+  __syncthreads();
+  cpx<R>* Z = fft_lds<true>(sm.a, sm.b, p.r_n1, TB, TB, 1, sm.tw, tid, nth);
+  for (int i = tid; i < n * TB; i += nth) {
+    const int q1 = i / TB, t = i - q1 * TB, nn = nb + t;
+    if (nn < Nt) V[((size_t)q1 * p.K2 + k2) * Nt + nn] = Z[i];
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_a(KP p, int TB, const cpx<R>* __restrict__ V,
+                                               R* __restrict__ U) {
+  extern __shared__ __align__(16) char smem[];
+  const int n = p.n2, tid = threadIdx.x, nth = blockDim.x;
+  Smem<R> sm = carve<R>(smem, n, TB);
+  const int q1 = blockIdx.x, pb = blockIdx.y * TB, npairs = p.Nt / 2, h2 = p.N2 / 2;
+  load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n2), n, tid, nth);
+  const cpx<R>* src = V + (size_t)q1 * p.K2 * p.Nt;
+  for (int i = tid; i < n * TB; i += nth) {
+    const int k = i / TB, pp = i - k * TB, pr = pb + pp;
+    cpx<R> c = {R(0), R(0)};
+    if (pr < npairs) {
+      if (k == 0) {
+        const cpx<R> a = src[2 * pr], b = src[2 * pr + 1];
+        c = {a.x, b.x};
+      } else if (k <= h2) {
+        const cpx<R> a = src[(size_t)k * p.Nt + 2 * pr], b = src[(size_t)k * p.Nt + 2 * pr + 1];
+        c = {(a.x - b.y) * R(0.5), (a.y + b.x) * R(0.5)};
+      } else if (k >= n - h2) {
+        const int kk = n - k;
+        const cpx<R> a = src[(size_t)kk * p.Nt + 2 * pr], b = src[(size_t)kk * p.Nt + 2 * pr + 1];
+        c = {(a.x + b.y) * R(0.5), (b.x - a.y) * R(0.5)};
+      }
+    }
+    sm.a[i] = c;
+  }
+  __syncthreads();
+  cpx<R>* Z = fft_lds<true>(sm.a, sm.b, p.r_n2, TB, TB, 1, sm.tw, tid, nth);
+  R* dst = U + (size_t)q1 * n * p.Nt;
+  for (int i = tid; i < n * TB; i += nth) {
+    const int q2 = i / TB, pp = i - q2 * TB, pr = pb + pp;
+    if (pr < npairs) *reinterpret_cast<cpx<R>*>(dst + (size_t)q2 * p.Nt + 2 * pr) = Z[i];
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+// Lines per workgroup: as many as fit 64 KB of LDS, at most 16.
+template <typename R>
+static int lines_for(int n) {
+  const size_t per = 2 * (size_t)n * sizeof(cpx<R>);
+  int tb = 16;
+  while (tb > 1 && per * tb + n * sizeof(cpx<R>) > 65536) tb >>= 1;
+  return tb;
+}
+
+template <typename R>
+static size_t smem_for(int n, int TB) {
+  return (size_t)n * sizeof(cpx<R>) * (2 * (size_t)TB + 1);
+}
+
+#define NEDNER_PASS_LAUNCH(KERNEL, NLEN, GX, GYLINES, IN_T, OUT_T)                                \
+  template <typename R>                                                                         \
+  static hipError_t run_##KERNEL(const KP& p, const void* in, void* out, hipStream_t s) {        \
+    const int n = (NLEN);                                                                       \
+    const int TB = lines_for<R>(n);                                                             \
+    const size_t sh = smem_for<R>(n, TB);                                                       \
+    dim3 grid((GX), ((GYLINES) + TB - 1) / TB);                                                 \
+    hipError_t e = allow_smem(KERNEL<R>, sh);                                                   \
+    if (e != hipSuccess) return e;                                                              \
+    hipLaunchKernelGGL((KERNEL<R>), grid, dim3(256), sh, s, p, TB,                              \
+                       static_cast<const IN_T*>(in), static_cast<OUT_T*>(out));                 \
+    return hipGetLastError();                                                                   \
+  }
+
+NEDNER_PASS_LAUNCH(k_lat_a, p.n2, p.n1, p.Nt / 2, R, cpx<R>)
+NEDNER_PASS_LAUNCH(k_lat_b, p.n1, p.K2, p.Nt, cpx<R>, cpx<R>)
+NEDNER_PASS_LAUNCH(k_pass_c, p.N1, p.K2, p.N3, cpx<R>, cpx<R>)
+NEDNER_PASS_LAUNCH(k_pass_d, p.N2, p.N1, p.N3 / 2, cpx<R>, R)
+NEDNER_PASS_LAUNCH(k_adj_d, p.N2, p.N1, p.N3 / 2, R, cpx<R>)
+NEDNER_PASS_LAUNCH(k_adj_c, p.N1, p.K2, p.N3, cpx<R>, cpx<R>)
+NEDNER_PASS_LAUNCH(k_adj_b, p.n1, p.K2, p.Nt, cpx<R>, cpx<R>)
+NEDNER_PASS_LAUNCH(k_adj_a, p.n2, p.n1, p.Nt / 2, cpx<R>, R)
+
+#define NEDNER_PASS_ENTRY(NAME, KERNEL)                                                   \
+  hipError_t NAME(const KP& p, const void* in, void* out, hipStream_t s) {                \
+    return p.prec == PREC_FP64 ? run_##KERNEL<double>(p, in, out, s)                      \
+                               : run_##KERNEL<float>(p, in, out, s);                      \
+  }
+
+NEDNER_PASS_ENTRY(launch_lat_a, k_lat_a)
+NEDNER_PASS_ENTRY(launch_lat_b, k_lat_b)
+NEDNER_PASS_ENTRY(launch_pass_c, k_pass_c)
+NEDNER_PASS_ENTRY(launch_pass_d, k_pass_d)
+NEDNER_PASS_ENTRY(launch_adj_d, k_adj_d)
+NEDNER_PASS_ENTRY(launch_adj_c, k_adj_c)
+NEDNER_PASS_ENTRY(launch_adj_b, k_adj_b)
+NEDNER_PASS_ENTRY(launch_adj_a, k_adj_a)
+
+}  // namespace nedner

@@ -1,0 +1,95 @@
+// Launch parameters shared by the host plan and the HIP kernels.
+//
+// One plain struct is passed by value to every kernel; it carries the sizes
+// of the operator, the scalar constants of the window, frequency and weight
+// (all reduced in double on the host) and the device tables of the plan.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_lds.hpp"
+
+namespace nedner {
+
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP32C = 2, PREC_FP32P = 3 };
+
+struct KP {
+  // ---- sizes -------------------------------------------------------------
+  int M;          // sensors
+  int Nt;         // time samples (even)
+  int N1, N2, N3; // output voxels (even)
+  int n1, n2;     // oversampled lateral grid sigma*N1, sigma*N2
+  int ntt;        // time FFT length sigma*Nt
+  int K2;         // half-spectrum columns along the second axis: N2/2 + 1
+  int J1;         // first-axis columns kept: N1 + 1 (both Nyquist representatives)
+  int W;          // window taps per dimension
+  int TT;         // time samples per lane in spreading
+  int S;          // rows per spreading sweep segment
+  int nseg;       // sweep segments along the first axis
+  int CB;         // stride of the per-(column, segment) cell offset table: S + W
+  int nchunk;     // time chunks of 64*TT samples
+  int prec;       // Prec
+
+  // ---- window and frequency constants (double, reduced on the host) -----
+  double beta;      // phi(x) = exp(-beta x^2), x in grid units, all three axes
+  double cdtnt;     // c * dt * ntt: x(j,l) = sign(l) cdtnt |K|/(2 pi)
+  double inv_L1sq;  // 1 / L1^2
+  double inv_L2sq;  // 1 / L2^2
+  double bz;        // 1 / (N3 d3)^2
+  double phase_p;   // (Nt/2 + t0/dt) / ntt: phase/(2 pi) = x * phase_p
+  double two_c;     // 2c
+  double scale_vol; // (dt/d3) / (N1 N2 N3)
+  double scale_spec;// dt/d3
+
+  // ---- device tables (types follow the precision) ------------------------
+  const void* w1;      // [M][W] weight type: s_m phi(o - f1), o = k - W/2 + 1
+  const void* w2;      // [M][W] weight type: phi(o - f2)
+  const int* cell;     // [M][2] (c1, c2)
+  const int* ent_m;    // spreading list: sensor of each entry
+  const void* ent_w2;  // spreading list: second-axis weight of each entry
+  const int* cellbeg;  // [n2 * nseg][CB] list offsets per sweep cell
+  const void* dec1;    // [J1] real: 1/phihat_1(j1), j1 = -N1/2..N1/2
+  const void* dec2;    // [K2] real: 1/phihat_2(k2), k2 = 0..N2/2
+  const void* dect;    // [Nt] real: 1/phihat_t(n - Nt/2)
+  const void* tw_n1;   // twiddles exp(-2 pi i k/n), complex of the data type
+  const void* tw_n2;
+  const void* tw_ntt;
+  const void* tw_N1;
+  const void* tw_N2;
+  const void* tw_N3;
+  Radices r_n1, r_n2, r_ntt, r_N1, r_N2, r_N3;
+};
+
+// Workspace buffers of one execute (device pointers).
+struct Bufs {
+  void* U;   // spread grid        [n1][n2][Nt] real
+  void* V;   // first FFT pass     [n1][K2][Nt] complex
+  void* G;   // NED result columns [K2][J1][Nt] complex
+  void* Z1;  // after depth IFFT   [K2][J1][N3] complex
+  void* Z2;  // after first-axis IFFT [K2][N1][N3] complex
+};
+
+// Allow a kernel more than 64 KB of dynamic LDS (gfx950 has 160 KB per CU).
+template <typename F>
+inline hipError_t allow_smem(F kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Host launchers (defined in the .hip files). All enqueue on `s` and return
+// the launch status.
+hipError_t launch_spread(const KP& p, const void* g, void* U, hipStream_t s);
+hipError_t launch_gather(const KP& p, const void* U, void* g, hipStream_t s);
+hipError_t launch_lat_a(const KP& p, const void* U, void* V, hipStream_t s);
+hipError_t launch_lat_b(const KP& p, const void* V, void* G, hipStream_t s);
+hipError_t launch_column(const KP& p, const void* G, void* out, int spectrum, hipStream_t s);
+hipError_t launch_pass_c(const KP& p, const void* Z1, void* Z2, hipStream_t s);
+hipError_t launch_pass_d(const KP& p, const void* Z2, void* vol, hipStream_t s);
+hipError_t launch_adj_d(const KP& p, const void* vol, void* Z2, hipStream_t s);
+hipError_t launch_adj_c(const KP& p, const void* Z2, void* Z1, hipStream_t s);
+hipError_t launch_column_adj(const KP& p, const void* Z1, void* G, hipStream_t s);
+hipError_t launch_adj_b(const KP& p, const void* G, void* V, hipStream_t s);
+hipError_t launch_adj_a(const KP& p, const void* V, void* U, hipStream_t s);
+
+}  // namespace nedner
