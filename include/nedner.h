@@ -74,7 +74,7 @@ typedef enum {
 typedef enum {
   NEDNER_FP64 = 0,              /* every step in double */
   NEDNER_FP32 = 1,              /* float data and arithmetic, double argument reduction */
-  NEDNER_FP32_COMPENSATED = 2,  /* as FP32, spreading accumulated in double registers */
+  NEDNER_FP32_COMPENSATED = 2,  /* as FP32, spreading sums carried in double registers */
   NEDNER_FP32_PLAIN = 3         /* float everywhere, arguments included */
 } nedner_precision;
 

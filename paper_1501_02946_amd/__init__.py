@@ -351,7 +351,9 @@ def lsq(plan: Plan, g, iters: int = 20, eta: float | None = None, x0=None, callb
     """
     torch = plan._torch
     if eta is None:
-        eta = 1.0 / max(power_norm(plan), 1e-300)
+        # a step just under 1/L (L = ||A||^2 estimated from below) keeps the
+        # projected iteration monotone
+        eta = 0.95 / max(power_norm(plan, iters=20), 1e-300)
     x = torch.zeros(plan.volume, dtype=plan.dtype, device=plan.device) if x0 is None else x0.clone()
     losses = []
     for it in range(iters):

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -84,7 +85,26 @@ struct Derived {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t real_size(int prec) { return prec == NEDNER_FP64 ? 8 : 4; }
-size_t weight_size(int prec) { return (prec == NEDNER_FP64 || prec == NEDNER_FP32_COMPENSATED) ? 8 : 4; }
+// Tuning overrides read at plan creation: NEDNER_SPREAD="depth,wide" sets the
+// spreading pipeline depth (1 or 2) and, for FP32C, 8-byte weights (0 or 1).
+struct SpreadOpt {
+  int pd = 2, wide = 1;
+};
+SpreadOpt spread_opt() {
+  SpreadOpt o;
+  if (const char* e = getenv("NEDNER_SPREAD")) {
+    int a = 0, b = 0;
+    if (sscanf(e, "%d,%d", &a, &b) == 2 && (a == 1 || a == 2)) {
+      o.pd = a;
+      o.wide = b != 0;
+    }
+  }
+  return o;
+}
+
+size_t weight_size(int prec) {
+  return prec == NEDNER_FP64 || (prec == NEDNER_FP32_COMPENSATED && spread_opt().wide) ? 8 : 4;
+}
 
 // Workspace: buffer 0 holds U, then G, then Z2; buffer 1 holds V, then Z1.
 void workspace_layout(const nedner_desc& d, const Derived& v, size_t* off1, size_t* total) {
@@ -100,10 +120,12 @@ void workspace_layout(const nedner_desc& d, const Derived& v, size_t* off1, size
   *total = b0 + b1;
 }
 
+// LDS of a column workgroup with one column: shared twiddles + one wave's buffers.
 size_t column_lds(const nedner_desc& d, const Derived& v) {
   const size_t rs = real_size(d.prec), cs = 2 * rs;
   const size_t nbuf = std::max<size_t>(v.ntt, d.n3);
-  return cs * (v.ntt + d.n3 + 2 * nbuf + d.n3 + 1) + (rs + 4) * (d.n3 + 1) + 16;
+  const size_t wave = (cs * (nbuf + d.n3 + 1) + (rs + 4) * (d.n3 + 1) + 15) & ~size_t(15);
+  return cs * (v.ntt + d.n3) + wave;
 }
 
 nedner_status validate_impl(const nedner_desc* d, Derived* out) {
@@ -166,18 +188,20 @@ nedner_status validate_impl(const nedner_desc* d, Derived* out) {
     return fail(NEDNER_E_UNSUPPORTED, "lateral transform longer than " + std::to_string(lat_max));
   if (column_lds(*d, v) > 160 * 1024)
     return fail(NEDNER_E_UNSUPPORTED, "time FFT length and depth count exceed the LDS of one workgroup");
+  // one wavefront transforms a column in place, at most 64 points per lane
+  if (v.ntt > 4096 || d->n3 > 4096)
+    return fail(NEDNER_E_UNSUPPORTED, "time FFT length or depth count above 4096");
   // spreading launch shape
   int TT = d->time_per_lane;
   if (TT == 0) TT = (d->nt >= 512 && d->nt % 4 == 0) ? 4 : (d->nt >= 128 ? 2 : 1);
+  if (d->nt % TT) return fail(NEDNER_E_ARG, "time_per_lane must divide nt");
   v.TT = TT;
   v.nchunk = int((d->nt + 64 * TT - 1) / (64 * TT));
   int S = d->rows_per_wave;
-  if (S == 0) {
-    const long waves1 = (long)v.n2 * v.nchunk;  // waves per segment
-    long nseg = (8192 + waves1 - 1) / waves1;
-    nseg = std::max(1L, std::min(nseg, std::max(1L, v.n1 / (2 * v.W))));
-    S = int((v.n1 + nseg - 1) / nseg);
-  }
+  // sweeps of 32 rows (at least 2W): shorter sweeps waste the W-1 warm-up
+  // cells, longer ones leave too few wavefronts to hide the load latency
+  // (measured on the 128^2 x 512 and 256^2 x 1024 workloads)
+  if (S == 0) S = std::max(32, 2 * v.W);
   S = int(std::min<long>(S, v.n1));
   v.S = S;
   v.nseg = int((v.n1 + S - 1) / S);
@@ -472,7 +496,10 @@ nedner_status create_one(const nedner_desc* desc, int device, nedner_plan* out) 
   for (int64_t n = 0; n < desc->nt; ++n) dtb[n] = 1.0 / phihat(v.beta, double(n - desc->nt / 2), double(v.ntt));
 
   DevAlloc A;
-  const bool wide = desc->prec == NEDNER_FP64 || desc->prec == NEDNER_FP32_COMPENSATED;
+  const SpreadOpt so = spread_opt();
+  k.spread_pd = so.pd;
+  k.wide_w = desc->prec == NEDNER_FP32_COMPENSATED && so.wide;
+  const bool wide = desc->prec == NEDNER_FP64 || k.wide_w;
   const bool dbl = desc->prec == NEDNER_FP64;
   k.w1 = wide ? A.upload(G.w1) : A.upload_as<float>(G.w1);
   k.w2 = wide ? A.upload(G.w2) : A.upload_as<float>(G.w2);

@@ -138,10 +138,18 @@ __device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ src, c
   }
 }
 
+// Make this wavefront's LDS writes visible to its own later LDS reads.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Full transform. Returns the buffer holding the result (a or b). Caller must
-// __syncthreads() before the call (data in `a` visible); on return the result
-// is visible to the whole workgroup.
-template <bool INV, typename T>
+// synchronise before the call (data in `a` visible); on return the result is
+// visible to every thread that took part. WAVE: the transform is done by one
+// wavefront alone (tid = lane, nth = 64) and only waits on its own LDS traffic.
+template <bool INV, typename T, bool WAVE = false>
 __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const Radices& rd, int lines, int ps, int ls,
                            const cpx<T>* tw, int tid, int nth) {
   int Ns = 1;
@@ -154,13 +162,94 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const Radices& rd, int lines, i
       case 5: stockham_stage<5, INV>(a, b, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
       default: stockham_stage<8, INV>(a, b, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
     }
-    __syncthreads();
+    if constexpr (WAVE)
+      wave_sync();
+    else
+      __syncthreads();
     cpx<T>* t = a;
     a = b;
     b = t;
     Ns *= R;
   }
   return a;
+}
+
+// In-place variant for a whole workgroup: each stage first gathers the inputs
+// of all of a thread's butterflies into registers, then (after a barrier)
+// writes the outputs over the same buffer. Half the LDS of the ping-pong form,
+// at the price of a second barrier per stage. K is the number of butterflies
+// a thread handles per stage (K * nth >= butterflies of the stage).
+template <bool WAVE>
+__device__ __forceinline__ void sync_policy() {
+  if constexpr (WAVE)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+// `lines` is a power of two; Ns (the product of the radices already done) is
+// one for power-of-two lengths, so the index arithmetic is shifts and masks
+// there and true divisions only for lengths with factors 3 or 5.
+template <int R, int K, bool INV, typename T, bool WAVE = false>
+__device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, int ps, int ls,
+                                         const cpx<T>* __restrict__ tw, int tid, int nth) {
+  const int nb = n / R;
+  const int total = nb * lines;
+  const int tstep = n / (Ns * R);
+  const int lsh = __builtin_ctz(lines);
+  const bool ns_pow2 = (Ns & (Ns - 1)) == 0;
+  cpx<T> v[K][R];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int t = tid + q * nth;
+    if (t < total) {
+      const int b = t & (lines - 1), j = t >> lsh;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * nb) * ps + b * ls];
+    }
+  }
+  sync_policy<WAVE>();
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int t = tid + q * nth;
+    if (t < total) {
+      const int b = t & (lines - 1), j = t >> lsh;
+      const int k = ns_pow2 ? (j & (Ns - 1)) : (j % Ns);
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[r * k * tstep];
+          v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
+        }
+      }
+      dft_small<R, INV>(v[q]);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(base + r * Ns) * ps + b * ls] = v[q][r];
+    }
+  }
+  sync_policy<WAVE>();
+}
+
+// Whole transform in place. PPT bounds the points per thread (n * lines <=
+// PPT * nth), which fixes the register array of every stage at compile time:
+// a thread holds ceil(PPT / R) butterflies of radix R. Caller synchronises
+// before; the result is in `buf` and visible on return.
+template <bool INV, typename T, bool WAVE, int PPT>
+__device__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, int ls, const cpx<T>* tw,
+                           int tid, int nth) {
+  int Ns = 1;
+  for (int s = 0; s < rd.count; ++s) {
+    const int R = rd.r[s];
+    switch (R) {
+      case 2: stage_ip<2, (PPT + 1) / 2, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+      case 3: stage_ip<3, (PPT + 2) / 3, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+      case 4: stage_ip<4, (PPT + 3) / 4, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+      case 5: stage_ip<5, (PPT + 4) / 5, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+      default: stage_ip<8, (PPT + 7) / 8, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+    }
+    Ns *= R;
+  }
 }
 
 // Stage a twiddle table of n entries from global memory into LDS.

@@ -114,71 +114,83 @@ __device__ __forceinline__ LPoint<R, ARGS64> lpoint(const KP& p, double a, int l
   return o;
 }
 
+// LDS of one workgroup: the two twiddle tables, shared, then per wavefront
+// (one column each) two transform buffers and the per-l arrays.
 template <typename R>
 struct ColSmem {
   cpx<R>* twt;  // ntt twiddles
   cpx<R>* tw3;  // N3 twiddles
-  cpx<R>* a;    // nbuf
-  cpx<R>* b;    // nbuf
+  cpx<R>* a;    // nbuf: the transform buffer (in place)
   cpx<R>* fl;   // N3 + 1
-  int* q0;      // N3 + 1 (adjoint)
   R* fr;        // N3 + 1 (adjoint)
+  int* q0;      // N3 + 1 (adjoint)
 };
 
 template <typename R>
-__device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p) {
+__host__ __device__ inline size_t col_wave_bytes(int ntt, int N3) {
+  const size_t nbuf = ntt > N3 ? ntt : N3;
+  size_t b = sizeof(cpx<R>) * (nbuf + N3 + 1) + (sizeof(R) + sizeof(int)) * ((size_t)N3 + 1);
+  return (b + 15) & ~size_t(15);
+}
+
+template <typename R>
+__host__ __device__ inline size_t col_shared_bytes(int ntt, int N3) {
+  return sizeof(cpx<R>) * ((size_t)ntt + N3);
+}
+
+template <typename R>
+__device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int wave) {
   ColSmem<R> s;
   const int nbuf = p.ntt > p.N3 ? p.ntt : p.N3;
   s.twt = reinterpret_cast<cpx<R>*>(smem);
   s.tw3 = s.twt + p.ntt;
-  s.a = s.tw3 + p.N3;
-  s.b = s.a + nbuf;
-  s.fl = s.b + nbuf;
+  char* w = smem + col_shared_bytes<R>(p.ntt, p.N3) + (size_t)wave * col_wave_bytes<R>(p.ntt, p.N3);
+  s.a = reinterpret_cast<cpx<R>*>(w);
+  s.fl = s.a + nbuf;
   s.fr = reinterpret_cast<R*>(s.fl + p.N3 + 1);
   s.q0 = reinterpret_cast<int*>(s.fr + p.N3 + 1);
   return s;
 }
 
-template <typename R>
-static size_t col_smem_bytes(const KP& p) {
-  const int nbuf = p.ntt > p.N3 ? p.ntt : p.N3;
-  return sizeof(cpx<R>) * ((size_t)p.ntt + p.N3 + 2 * (size_t)nbuf + p.N3 + 1) +
-         (sizeof(R) + sizeof(int)) * ((size_t)p.N3 + 1) + 16;
-}
-
+// One wavefront per column; a workgroup of CPW wavefronts shares the twiddles.
 // SPEC: write the full spectrum F (N1, N2, N3) in FFT order instead of Z1.
-template <typename R, int W, bool ARGS64, bool SPEC>
-__global__ __launch_bounds__(256) void k_column(KP p, const cpx<R>* __restrict__ G, void* out) {
+template <typename R, int W, bool ARGS64, bool SPEC, int PPT>
+__global__ __launch_bounds__(512) void k_column(KP p, int ncol, const cpx<R>* __restrict__ G, void* out) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int je = blockIdx.x, k2 = blockIdx.y;
+  const int lane = tid & 63, wave = tid >> 6;
   const int ntt = p.ntt, N3 = p.N3, Nt = p.Nt, h3 = N3 / 2;
-  const size_t col = (size_t)k2 * p.J1 + je;
+  ColSmem<R> sm = col_carve<R>(smem, p, wave);
+  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
+  load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
+  __syncthreads();
+  const int cidx = __builtin_amdgcn_readfirstlane(blockIdx.x * (nth >> 6) + wave);
+  if (cidx >= ncol) return;
+  const int k2 = cidx / p.J1, je = cidx - k2 * p.J1;
+  const size_t col = cidx;
   double fac;
   int pol;
   column_policy(je, k2, p.N1, p.N2, fac, pol);
   if (!SPEC && fac == 0.0) {
     cpx<R>* z1 = static_cast<cpx<R>*>(out) + col * N3;
-    for (int i = tid; i < N3; i += nth) z1[i] = cpx<R>{R(0), R(0)};
+    for (int i = lane; i < N3; i += 64) z1[i] = cpx<R>{R(0), R(0)};
     return;
   }
-  ColSmem<R> sm = col_carve<R>(smem, p);
-  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
-  load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
   const cpx<R>* gc = G + col * Nt;
-  for (int s = tid; s < ntt; s += nth) {
+  for (int s = lane; s < ntt; s += 64) {
     // slot s holds n' = s (s < ntt/2) or s - ntt; data index n = n' + Nt/2
     const int np = s < ntt / 2 ? s : s - ntt;
     const int n = np + Nt / 2;
     sm.a[s] = (n >= 0 && n < Nt) ? gc[n] : cpx<R>{R(0), R(0)};
   }
-  __syncthreads();
-  cpx<R>* B = fft_lds<false>(sm.a, sm.b, p.r_ntt, 1, 1, 0, sm.twt, tid, nth);
+  wave_sync();
+  fft_lds_ip<false, R, true, PPT>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, lane, 64);
+  const cpx<R>* B = sm.a;
   const int j1 = je - p.N1 / 2;
   const double a = double(j1) * double(j1) * p.inv_L1sq + double(k2) * double(k2) * p.inv_L2sq;
   const double scale = SPEC ? p.scale_spec : p.scale_vol;
   const R beta = R(p.beta);
-  for (int li = tid; li <= N3; li += nth) {
+  for (int li = lane; li <= N3; li += 64) {
     const int l = li - h3;
     const LPoint<R, ARGS64> lp = lpoint<R, ARGS64>(p, a, l, scale);
     cpx<R> H = {R(0), R(0)};
@@ -191,7 +203,7 @@ __global__ __launch_bounds__(256) void k_column(KP p, const cpx<R>* __restrict__
     }
     sm.fl[li] = cmul(H, lp.ph) * lp.wgt;
   }
-  __syncthreads();
+  wave_sync();
   if constexpr (SPEC) {
     cpx<R>* F = static_cast<cpx<R>*>(out);
     const int N1 = p.N1, N2 = p.N2;
@@ -199,17 +211,16 @@ __global__ __launch_bounds__(256) void k_column(KP p, const cpx<R>* __restrict__
     const bool mirror = k2 >= 1 && je >= 1;
     const size_t rd = ((size_t)pmodc(j1, N1) * N2 + k2) * N3;
     const size_t rm = ((size_t)pmodc(-j1, N1) * N2 + pmodc(-k2, N2)) * N3;
-    for (int li = tid; li <= N3; li += nth) {
+    for (int li = lane; li <= N3; li += 64) {
       const int l = li - h3;
       if (direct && li < N3) F[rd + pmodc(l, N3)] = sm.fl[li];
       if (mirror && li > 0) F[rm + pmodc(-l, N3)] = conjg(sm.fl[li]);
     }
   } else {
-    // X[slot] for the depth inverse; B is free again, the other buffer too
+    // X[slot] for the depth inverse; the transform buffer is free again
     cpx<R>* X = sm.a;
-    cpx<R>* Y = sm.b;
     const R f = R(fac);
-    for (int s = tid; s < N3; s += nth) {
+    for (int s = lane; s < N3; s += 64) {
       cpx<R> v;
       if (s == h3) {
         const cpx<R> lo = sm.fl[0], hi = sm.fl[N3];
@@ -220,10 +231,11 @@ __global__ __launch_bounds__(256) void k_column(KP p, const cpx<R>* __restrict__
       }
       X[s] = v * f;
     }
-    __syncthreads();
-    cpx<R>* Zr = fft_lds<true>(X, Y, p.r_N3, 1, 1, 0, sm.tw3, tid, nth);
+    wave_sync();
+    fft_lds_ip<true, R, true, PPT>(X, p.r_N3, 1, 1, 0, sm.tw3, lane, 64);
+    const cpx<R>* Zr = X;
     cpx<R>* z1 = static_cast<cpx<R>*>(out) + col * N3;
-    for (int i = tid; i < N3; i += nth) z1[i] = Zr[i];
+    for (int i = lane; i < N3; i += 64) z1[i] = Zr[i];
   }
 }
 
@@ -239,36 +251,41 @@ __device__ __forceinline__ int lower_bound_i(const int* q, int lo, int hi, int v
   return lo;
 }
 
-template <typename R, int W, bool ARGS64>
-__global__ __launch_bounds__(256) void k_column_adj(KP p, int mwrap, const cpx<R>* __restrict__ Z1,
+template <typename R, int W, bool ARGS64, int PPT>
+__global__ __launch_bounds__(512) void k_column_adj(KP p, int ncol, int mwrap, const cpx<R>* __restrict__ Z1,
                                                     cpx<R>* __restrict__ G) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int je = blockIdx.x, k2 = blockIdx.y;
+  const int lane = tid & 63, wave = tid >> 6;
   const int ntt = p.ntt, N3 = p.N3, Nt = p.Nt, h3 = N3 / 2;
-  const size_t col = (size_t)k2 * p.J1 + je;
+  ColSmem<R> sm = col_carve<R>(smem, p, wave);
+  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
+  load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
+  __syncthreads();
+  const int cidx = __builtin_amdgcn_readfirstlane(blockIdx.x * (nth >> 6) + wave);
+  if (cidx >= ncol) return;
+  const int k2 = cidx / p.J1, je = cidx - k2 * p.J1;
+  const size_t col = cidx;
   double fac;
   int pol;
   column_policy(je, k2, p.N1, p.N2, fac, pol);
   cpx<R>* gc = G + col * Nt;
   if (fac == 0.0) {
-    for (int i = tid; i < Nt; i += nth) gc[i] = cpx<R>{R(0), R(0)};
+    for (int i = lane; i < Nt; i += 64) gc[i] = cpx<R>{R(0), R(0)};
     return;
   }
-  ColSmem<R> sm = col_carve<R>(smem, p);
-  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
-  load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
   const cpx<R>* zc = Z1 + col * N3;
-  for (int i = tid; i < N3; i += nth) sm.a[i] = zc[i];
-  __syncthreads();
+  for (int i = lane; i < N3; i += 64) sm.a[i] = zc[i];
+  wave_sync();
   // transpose of the unnormalised depth inverse: forward FFT
-  cpx<R>* Xp = fft_lds<false>(sm.a, sm.b, p.r_N3, 1, 1, 0, sm.tw3, tid, nth);
+  fft_lds_ip<false, R, true, PPT>(sm.a, p.r_N3, 1, 1, 0, sm.tw3, lane, 64);
+  const cpx<R>* Xp = sm.a;
   const int j1 = je - p.N1 / 2;
   const double a = double(j1) * double(j1) * p.inv_L1sq + double(k2) * double(k2) * p.inv_L2sq;
   const R f = R(fac);
   const R mlo = pol == 0 ? R(1) : (pol == 1 ? R(0) : R(0.5));
   const R mhi = pol == 1 ? R(1) : (pol == 0 ? R(0) : R(0.5));
-  for (int li = tid; li <= N3; li += nth) {
+  for (int li = lane; li <= N3; li += 64) {
     const int l = li - h3;
     cpx<R> fp;
     if (li == 0)
@@ -282,12 +299,12 @@ __global__ __launch_bounds__(256) void k_column_adj(KP p, int mwrap, const cpx<R
     sm.q0[li] = lp.q0;
     sm.fr[li] = lp.fr;
   }
-  __syncthreads();
+  wave_sync();
   // B'[q] = sum over l whose taps cover q of phi(x_l - q) H'(l); x_l is
   // non-decreasing in l, so the l covering q form a contiguous range.
-  cpx<R>* Bp = (Xp == sm.a) ? sm.b : sm.a;
+  cpx<R>* Bp = sm.a;
   const R beta = R(p.beta);
-  for (int q = tid; q < ntt; q += nth) {
+  for (int q = lane; q < ntt; q += 64) {
     const int qc = q < ntt / 2 ? q : q - ntt;
     cpx<R> acc = {R(0), R(0)};
     for (int m = -mwrap; m <= mwrap; ++m) {
@@ -302,10 +319,10 @@ __global__ __launch_bounds__(256) void k_column_adj(KP p, int mwrap, const cpx<R
     }
     Bp[q] = acc;
   }
-  __syncthreads();
-  cpx<R>* other = (Bp == sm.a) ? sm.b : sm.a;
-  cpx<R>* Ap = fft_lds<true>(Bp, other, p.r_ntt, 1, 1, 0, sm.twt, tid, nth);
-  for (int n = tid; n < Nt; n += nth) {
+  wave_sync();
+  fft_lds_ip<true, R, true, PPT>(Bp, p.r_ntt, 1, 1, 0, sm.twt, lane, 64);
+  const cpx<R>* Ap = Bp;
+  for (int n = lane; n < Nt; n += 64) {
     const int s = pmodc(n - Nt / 2, ntt);
     gc[n] = Ap[s];
   }
@@ -313,35 +330,88 @@ __global__ __launch_bounds__(256) void k_column_adj(KP p, int mwrap, const cpx<R
 
 // ---------------------------------------------------------------- launchers
 
-template <typename R, int W, bool ARGS64>
-static hipError_t column_w(const KP& p, const void* G, void* out, int spec, hipStream_t s) {
-  const size_t sh = col_smem_bytes<R>(p);
-  dim3 grid(p.J1, p.K2);
-  hipError_t e = allow_smem(spec ? k_column<R, W, ARGS64, true> : k_column<R, W, ARGS64, false>, sh);
+// Columns (wavefronts) per workgroup: the count in 1..8 that keeps the most
+// wavefronts resident on a CU with 160 KB of LDS (the twiddles are shared).
+template <typename R>
+static int cols_per_wg(const KP& p) {
+  const size_t sh = col_shared_bytes<R>(p.ntt, p.N3), per = col_wave_bytes<R>(p.ntt, p.N3);
+  const size_t lds = 160 * 1024;
+  int best = 1;
+  size_t best_waves = 0;
+  for (int c = 1; c <= 8; ++c) {
+    const size_t wg = sh + c * per;
+    if (wg > lds) break;
+    const size_t waves = c * (lds / wg);
+    if (waves > best_waves) {
+      best_waves = waves;
+      best = c;
+    }
+  }
+  return best;
+}
+
+// Points per lane of the per-column transforms (the larger of ntt and N3 over 64).
+static int column_ppt(const KP& p) {
+  const int n = p.ntt > p.N3 ? p.ntt : p.N3;
+  const int need = (n + 63) / 64;
+  return need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
+}
+
+template <typename R, int W, bool ARGS64, int PPT>
+static hipError_t column_wp(const KP& p, const void* G, void* out, int spec, hipStream_t s) {
+  const int cpw = cols_per_wg<R>(p);
+  const int ncol = p.J1 * p.K2;
+  const size_t sh = col_shared_bytes<R>(p.ntt, p.N3) + cpw * col_wave_bytes<R>(p.ntt, p.N3);
+  dim3 grid((ncol + cpw - 1) / cpw);
+  hipError_t e = allow_smem(spec ? k_column<R, W, ARGS64, true, PPT> : k_column<R, W, ARGS64, false, PPT>, sh);
   if (e != hipSuccess) return e;
   if (spec)
-    hipLaunchKernelGGL((k_column<R, W, ARGS64, true>), grid, dim3(256), sh, s, p,
+    hipLaunchKernelGGL((k_column<R, W, ARGS64, true, PPT>), grid, dim3(64 * cpw), sh, s, p, ncol,
                        static_cast<const cpx<R>*>(G), out);
   else
-    hipLaunchKernelGGL((k_column<R, W, ARGS64, false>), grid, dim3(256), sh, s, p,
+    hipLaunchKernelGGL((k_column<R, W, ARGS64, false, PPT>), grid, dim3(64 * cpw), sh, s, p, ncol,
                        static_cast<const cpx<R>*>(G), out);
   return hipGetLastError();
 }
 
-template <typename R, int W, bool ARGS64>
-static hipError_t column_adj_w(const KP& p, const void* Z1, void* G, hipStream_t s) {
-  const size_t sh = col_smem_bytes<R>(p);
-  dim3 grid(p.J1, p.K2);
+template <typename R, int W, bool ARGS64, int PPT>
+static hipError_t column_adj_wp(const KP& p, const void* Z1, void* G, hipStream_t s) {
+  const int cpw = cols_per_wg<R>(p);
+  const int ncol = p.J1 * p.K2;
+  const size_t sh = col_shared_bytes<R>(p.ntt, p.N3) + cpw * col_wave_bytes<R>(p.ntt, p.N3);
+  dim3 grid((ncol + cpw - 1) / cpw);
   // number of periodic images of the time grid a tap window can reach
   const double xmax = p.cdtnt * sqrt((p.N1 / 2.0) * (p.N1 / 2.0) * p.inv_L1sq +
                                      (p.N2 / 2.0) * (p.N2 / 2.0) * p.inv_L2sq +
                                      (p.N3 / 2.0) * (p.N3 / 2.0) * p.bz);
   const int mwrap = 1 + int((xmax + W) / p.ntt);
-  hipError_t e = allow_smem(k_column_adj<R, W, ARGS64>, sh);
+  hipError_t e = allow_smem(k_column_adj<R, W, ARGS64, PPT>, sh);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_column_adj<R, W, ARGS64>), grid, dim3(256), sh, s, p, mwrap,
+  hipLaunchKernelGGL((k_column_adj<R, W, ARGS64, PPT>), grid, dim3(64 * cpw), sh, s, p, ncol, mwrap,
                      static_cast<const cpx<R>*>(Z1), static_cast<cpx<R>*>(G));
   return hipGetLastError();
+}
+
+template <typename R, int W, bool ARGS64>
+static hipError_t column_w(const KP& p, const void* G, void* out, int spec, hipStream_t s) {
+  switch (column_ppt(p)) {
+    case 4: return column_wp<R, W, ARGS64, 4>(p, G, out, spec, s);
+    case 8: return column_wp<R, W, ARGS64, 8>(p, G, out, spec, s);
+    case 16: return column_wp<R, W, ARGS64, 16>(p, G, out, spec, s);
+    case 32: return column_wp<R, W, ARGS64, 32>(p, G, out, spec, s);
+    default: return column_wp<R, W, ARGS64, 64>(p, G, out, spec, s);
+  }
+}
+
+template <typename R, int W, bool ARGS64>
+static hipError_t column_adj_w(const KP& p, const void* Z1, void* G, hipStream_t s) {
+  switch (column_ppt(p)) {
+    case 4: return column_adj_wp<R, W, ARGS64, 4>(p, Z1, G, s);
+    case 8: return column_adj_wp<R, W, ARGS64, 8>(p, Z1, G, s);
+    case 16: return column_adj_wp<R, W, ARGS64, 16>(p, Z1, G, s);
+    case 32: return column_adj_wp<R, W, ARGS64, 32>(p, Z1, G, s);
+    default: return column_adj_wp<R, W, ARGS64, 64>(p, Z1, G, s);
+  }
 }
 
 template <typename R, bool ARGS64>

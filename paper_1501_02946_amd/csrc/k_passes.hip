@@ -14,6 +14,9 @@
 // with the Stockham engine, and writes the tile back with the per-pass
 // pre/post-processing fused in. Two real lines are packed into one complex
 // line for the real transforms (lat_a, pass_d, adj_d, adj_a).
+#include <cstdio>
+#include <cstdlib>
+
 #include "kparams.hpp"
 
 namespace nedner {
@@ -27,7 +30,7 @@ template <typename R>
 struct Smem {
   cpx<R>* tw;
   cpx<R>* a;
-  cpx<R>* b;
+  cpx<R>* b;  // second buffer of the ping-pong form
 };
 
 template <typename R>
@@ -39,15 +42,28 @@ __device__ __forceinline__ Smem<R> carve(char* smem, int n, int TB) {
   return s;
 }
 
+// The batched transform of a pass: ping-pong (one barrier per stage, two
+// buffers) or in place (two barriers per stage, one buffer). Returns the
+// buffer that holds the result.
+template <bool INV, typename R, bool IP>
+__device__ __forceinline__ cpx<R>* pass_fft(Smem<R>& sm, const Radices& rd, int TB, int tid, int nth) {
+  if constexpr (IP) {
+    fft_lds_ip<INV, R, false, 8>(sm.a, rd, TB, TB, 1, sm.tw, tid, nth);
+    return sm.a;
+  } else {
+    return fft_lds<INV, R, false>(sm.a, sm.b, rd, TB, TB, 1, sm.tw, tid, nth);
+  }
+}
+
 // ---------------------------------------------------------------- forward
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_lat_a(KP p, int TB, const R* __restrict__ U,
+template <typename R, bool IP>
+__device__ __forceinline__ void lat_a_body(const KP& p, int TB, int bx, int by, const R* __restrict__ U,
                                                cpx<R>* __restrict__ V) {
   extern __shared__ __align__(16) char smem[];
   const int n = p.n2, tid = threadIdx.x, nth = blockDim.x;
   Smem<R> sm = carve<R>(smem, n, TB);
-  const int q1 = blockIdx.x, pb = blockIdx.y * TB, npairs = p.Nt / 2;
+  const int q1 = by, pb = bx * TB, npairs = p.Nt / 2;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n2), n, tid, nth);
   const R* src = U + (size_t)q1 * n * p.Nt;
   for (int i = tid; i < n * TB; i += nth) {
@@ -57,7 +73,7 @@ __global__ __launch_bounds__(256) void k_lat_a(KP p, int TB, const R* __restrict
     sm.a[i] = z;
   }
   __syncthreads();
-  cpx<R>* Z = fft_lds<false>(sm.a, sm.b, p.r_n2, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* Z = pass_fft<false, R, IP>(sm, p.r_n2, TB, tid, nth);
   cpx<R>* dst = V + (size_t)q1 * p.K2 * p.Nt;
   for (int i = tid; i < p.K2 * TB; i += nth) {
     const int k = i / TB, pp = i - k * TB, pr = pb + pp;
@@ -71,13 +87,19 @@ __global__ __launch_bounds__(256) void k_lat_a(KP p, int TB, const R* __restrict
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_lat_b(KP p, int TB, const cpx<R>* __restrict__ V,
+template <typename R, bool IP>
+__global__ __launch_bounds__(512) void k_lat_a(KP p, int TB, const R* __restrict__ U,
+                                               cpx<R>* __restrict__ V) {
+  lat_a_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, U, V);
+}
+
+template <typename R, bool IP>
+__device__ __forceinline__ void lat_b_body(const KP& p, int TB, int bx, int by, const cpx<R>* __restrict__ V,
                                                cpx<R>* __restrict__ G) {
   extern __shared__ __align__(16) char smem[];
   const int n = p.n1, tid = threadIdx.x, nth = blockDim.x;
   Smem<R> sm = carve<R>(smem, n, TB);
-  const int k2 = blockIdx.x, nb = blockIdx.y * TB, Nt = p.Nt;
+  const int k2 = by, nb = bx * TB, Nt = p.Nt;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n1), n, tid, nth);
   for (int i = tid; i < n * TB; i += nth) {
     const int q1 = i / TB, t = i - q1 * TB, nn = nb + t;
@@ -86,7 +108,7 @@ __global__ __launch_bounds__(256) void k_lat_b(KP p, int TB, const cpx<R>* __res
     sm.a[i] = z;
   }
   __syncthreads();
-  cpx<R>* Z = fft_lds<false>(sm.a, sm.b, p.r_n1, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* Z = pass_fft<false, R, IP>(sm, p.r_n1, TB, tid, nth);
   const R* d1 = static_cast<const R*>(p.dec1);
   const R* dt = static_cast<const R*>(p.dect);
   const R d2 = static_cast<const R*>(p.dec2)[k2];
@@ -98,13 +120,19 @@ __global__ __launch_bounds__(256) void k_lat_b(KP p, int TB, const cpx<R>* __res
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_pass_c(KP p, int TB, const cpx<R>* __restrict__ Z1,
+template <typename R, bool IP>
+__global__ __launch_bounds__(512) void k_lat_b(KP p, int TB, const cpx<R>* __restrict__ V,
+                                               cpx<R>* __restrict__ G) {
+  lat_b_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, V, G);
+}
+
+template <typename R, bool IP>
+__device__ __forceinline__ void pass_c_body(const KP& p, int TB, int bx, int by, const cpx<R>* __restrict__ Z1,
                                                 cpx<R>* __restrict__ Z2) {
   extern __shared__ __align__(16) char smem[];
   const int n = p.N1, tid = threadIdx.x, nth = blockDim.x;
   Smem<R> sm = carve<R>(smem, n, TB);
-  const int k2 = blockIdx.x, ib = blockIdx.y * TB, N3 = p.N3;
+  const int k2 = by, ib = bx * TB, N3 = p.N3;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N1), n, tid, nth);
   const cpx<R>* src = Z1 + (size_t)k2 * p.J1 * N3;
   for (int i = tid; i < n * TB; i += nth) {
@@ -118,7 +146,7 @@ __global__ __launch_bounds__(256) void k_pass_c(KP p, int TB, const cpx<R>* __re
     sm.a[i] = z;
   }
   __syncthreads();
-  cpx<R>* Z = fft_lds<true>(sm.a, sm.b, p.r_N1, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* Z = pass_fft<true, R, IP>(sm, p.r_N1, TB, tid, nth);
   cpx<R>* dst = Z2 + (size_t)k2 * n * N3;
   for (int i = tid; i < n * TB; i += nth) {
     const int i1 = i / TB, t = i - i1 * TB, i3 = ib + t;
@@ -126,13 +154,19 @@ __global__ __launch_bounds__(256) void k_pass_c(KP p, int TB, const cpx<R>* __re
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_pass_d(KP p, int TB, const cpx<R>* __restrict__ Z2,
+template <typename R, bool IP>
+__global__ __launch_bounds__(512) void k_pass_c(KP p, int TB, const cpx<R>* __restrict__ Z1,
+                                                cpx<R>* __restrict__ Z2) {
+  pass_c_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, Z1, Z2);
+}
+
+template <typename R, bool IP>
+__device__ __forceinline__ void pass_d_body(const KP& p, int TB, int bx, int by, const cpx<R>* __restrict__ Z2,
                                                 R* __restrict__ vol) {
   extern __shared__ __align__(16) char smem[];
   const int n = p.N2, tid = threadIdx.x, nth = blockDim.x;
   Smem<R> sm = carve<R>(smem, n, TB);
-  const int i1 = blockIdx.x, pb = blockIdx.y * TB, N3 = p.N3, npairs = N3 / 2, h = n / 2;
+  const int i1 = by, pb = bx * TB, N3 = p.N3, npairs = N3 / 2, h = n / 2;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N2), n, tid, nth);
   for (int i = tid; i < n * TB; i += nth) {
     const int k = i / TB, pp = i - k * TB, pr = pb + pp;
@@ -151,7 +185,7 @@ __global__ __launch_bounds__(256) void k_pass_d(KP p, int TB, const cpx<R>* __re
     sm.a[i] = c;
   }
   __syncthreads();
-  cpx<R>* Z = fft_lds<true>(sm.a, sm.b, p.r_N2, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* Z = pass_fft<true, R, IP>(sm, p.r_N2, TB, tid, nth);
   R* dst = vol + (size_t)i1 * n * N3;
   for (int i = tid; i < n * TB; i += nth) {
     const int i2 = i / TB, pp = i - i2 * TB, pr = pb + pp;
@@ -159,15 +193,21 @@ __global__ __launch_bounds__(256) void k_pass_d(KP p, int TB, const cpx<R>* __re
   }
 }
 
+template <typename R, bool IP>
+__global__ __launch_bounds__(512) void k_pass_d(KP p, int TB, const cpx<R>* __restrict__ Z2,
+                                                R* __restrict__ vol) {
+  pass_d_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, Z2, vol);
+}
+
 // ---------------------------------------------------------------- adjoint
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_adj_d(KP p, int TB, const R* __restrict__ vol,
+template <typename R, bool IP>
+__device__ __forceinline__ void adj_d_body(const KP& p, int TB, int bx, int by, const R* __restrict__ vol,
                                                cpx<R>* __restrict__ Z2) {
   extern __shared__ __align__(16) char smem[];
   const int n = p.N2, tid = threadIdx.x, nth = blockDim.x;
   Smem<R> sm = carve<R>(smem, n, TB);
-  const int i1 = blockIdx.x, pb = blockIdx.y * TB, N3 = p.N3, npairs = N3 / 2, h = n / 2;
+  const int i1 = by, pb = bx * TB, N3 = p.N3, npairs = N3 / 2, h = n / 2;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N2), n, tid, nth);
   const R* src = vol + (size_t)i1 * n * N3;
   for (int i = tid; i < n * TB; i += nth) {
@@ -177,7 +217,7 @@ __global__ __launch_bounds__(256) void k_adj_d(KP p, int TB, const R* __restrict
     sm.a[i] = z;
   }
   __syncthreads();
-  cpx<R>* Z = fft_lds<false>(sm.a, sm.b, p.r_N2, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* Z = pass_fft<false, R, IP>(sm, p.r_N2, TB, tid, nth);
   for (int i = tid; i < (h + 1) * TB; i += nth) {
     const int k = i / TB, pp = i - k * TB, pr = pb + pp;
     if (pr >= npairs) continue;
@@ -192,13 +232,19 @@ __global__ __launch_bounds__(256) void k_adj_d(KP p, int TB, const R* __restrict
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_adj_c(KP p, int TB, const cpx<R>* __restrict__ Z2,
+template <typename R, bool IP>
+__global__ __launch_bounds__(512) void k_adj_d(KP p, int TB, const R* __restrict__ vol,
+                                               cpx<R>* __restrict__ Z2) {
+  adj_d_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, vol, Z2);
+}
+
+template <typename R, bool IP>
+__device__ __forceinline__ void adj_c_body(const KP& p, int TB, int bx, int by, const cpx<R>* __restrict__ Z2,
                                                cpx<R>* __restrict__ Z1) {
   extern __shared__ __align__(16) char smem[];
   const int n = p.N1, tid = threadIdx.x, nth = blockDim.x;
   Smem<R> sm = carve<R>(smem, n, TB);
-  const int k2 = blockIdx.x, ib = blockIdx.y * TB, N3 = p.N3;
+  const int k2 = by, ib = bx * TB, N3 = p.N3;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N1), n, tid, nth);
   const cpx<R>* src = Z2 + (size_t)k2 * n * N3;
   for (int i = tid; i < n * TB; i += nth) {
@@ -208,7 +254,7 @@ __global__ __launch_bounds__(256) void k_adj_c(KP p, int TB, const cpx<R>* __res
     sm.a[i] = z;
   }
   __syncthreads();
-  cpx<R>* Z = fft_lds<false>(sm.a, sm.b, p.r_N1, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* Z = pass_fft<false, R, IP>(sm, p.r_N1, TB, tid, nth);
   cpx<R>* dst = Z1 + (size_t)k2 * p.J1 * N3;
   for (int i = tid; i < p.J1 * TB; i += nth) {
     const int je = i / TB, t = i - je * TB, i3 = ib + t;
@@ -218,13 +264,19 @@ __global__ __launch_bounds__(256) void k_adj_c(KP p, int TB, const cpx<R>* __res
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_adj_b(KP p, int TB, const cpx<R>* __restrict__ G,
+template <typename R, bool IP>
+__global__ __launch_bounds__(512) void k_adj_c(KP p, int TB, const cpx<R>* __restrict__ Z2,
+                                               cpx<R>* __restrict__ Z1) {
+  adj_c_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, Z2, Z1);
+}
+
+template <typename R, bool IP>
+__device__ __forceinline__ void adj_b_body(const KP& p, int TB, int bx, int by, const cpx<R>* __restrict__ G,
                                                cpx<R>* __restrict__ V) {
   extern __shared__ __align__(16) char smem[];
   const int n = p.n1, tid = threadIdx.x, nth = blockDim.x;
   Smem<R> sm = carve<R>(smem, n, TB);
-  const int k2 = blockIdx.x, nb = blockIdx.y * TB, Nt = p.Nt, h1 = p.N1 / 2;
+  const int k2 = by, nb = bx * TB, Nt = p.Nt, h1 = p.N1 / 2;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n1), n, tid, nth);
   const R* d1 = static_cast<const R*>(p.dec1);
   const R* dt = static_cast<const R*>(p.dect);
@@ -240,20 +292,26 @@ __global__ __launch_bounds__(256) void k_adj_b(KP p, int TB, const cpx<R>* __res
     sm.a[i] = z;
   }
   __syncthreads();
-  cpx<R>* Z = fft_lds<true>(sm.a, sm.b, p.r_n1, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* Z = pass_fft<true, R, IP>(sm, p.r_n1, TB, tid, nth);
   for (int i = tid; i < n * TB; i += nth) {
     const int q1 = i / TB, t = i - q1 * TB, nn = nb + t;
     if (nn < Nt) V[((size_t)q1 * p.K2 + k2) * Nt + nn] = Z[i];
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_adj_a(KP p, int TB, const cpx<R>* __restrict__ V,
+template <typename R, bool IP>
+__global__ __launch_bounds__(512) void k_adj_b(KP p, int TB, const cpx<R>* __restrict__ G,
+                                               cpx<R>* __restrict__ V) {
+  adj_b_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, G, V);
+}
+
+template <typename R, bool IP>
+__device__ __forceinline__ void adj_a_body(const KP& p, int TB, int bx, int by, const cpx<R>* __restrict__ V,
                                                R* __restrict__ U) {
   extern __shared__ __align__(16) char smem[];
   const int n = p.n2, tid = threadIdx.x, nth = blockDim.x;
   Smem<R> sm = carve<R>(smem, n, TB);
-  const int q1 = blockIdx.x, pb = blockIdx.y * TB, npairs = p.Nt / 2, h2 = p.N2 / 2;
+  const int q1 = by, pb = bx * TB, npairs = p.Nt / 2, h2 = p.N2 / 2;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n2), n, tid, nth);
   const cpx<R>* src = V + (size_t)q1 * p.K2 * p.Nt;
   for (int i = tid; i < n * TB; i += nth) {
@@ -275,7 +333,7 @@ __global__ __launch_bounds__(256) void k_adj_a(KP p, int TB, const cpx<R>* __res
     sm.a[i] = c;
   }
   __syncthreads();
-  cpx<R>* Z = fft_lds<true>(sm.a, sm.b, p.r_n2, TB, TB, 1, sm.tw, tid, nth);
+  cpx<R>* Z = pass_fft<true, R, IP>(sm, p.r_n2, TB, tid, nth);
   R* dst = U + (size_t)q1 * n * p.Nt;
   for (int i = tid; i < n * TB; i += nth) {
     const int q2 = i / TB, pp = i - q2 * TB, pr = pb + pp;
@@ -283,33 +341,58 @@ __global__ __launch_bounds__(256) void k_adj_a(KP p, int TB, const cpx<R>* __res
   }
 }
 
+template <typename R, bool IP>
+__global__ __launch_bounds__(512) void k_adj_a(KP p, int TB, const cpx<R>* __restrict__ V,
+                                               R* __restrict__ U) {
+  adj_a_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, V, U);
+}
+
 // ---------------------------------------------------------------- launchers
 
-// Lines per workgroup: as many as fit 64 KB of LDS, at most 16.
-template <typename R>
-static int lines_for(int n) {
-  const size_t per = 2 * (size_t)n * sizeof(cpx<R>);
-  int tb = 16;
-  while (tb > 1 && per * tb + n * sizeof(cpx<R>) > 65536) tb >>= 1;
-  return tb;
+// Launch shape of the batched passes: lines per workgroup, threads per
+// workgroup and the transform form. The default, measured best on the C2/C3
+// workloads, is the in-place form with 16 lines (whole 128-byte rows of float
+// pairs) and 512 threads; NEDNER_PASS_SHAPE ("lines,threads,inplace")
+// overrides it for tuning.
+struct PassShape {
+  int tb, threads, ip;
+};
+
+static PassShape pass_shape(int n, size_t cs) {
+  PassShape s{16, 512, 1};
+  if (const char* e = getenv("NEDNER_PASS_SHAPE")) {
+    int a = 0, b = 0, c = 0;
+    if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a > 0 && (a & (a - 1)) == 0 && b >= 64 && b <= 512 &&
+        b % 64 == 0)
+      s = PassShape{a, b, c != 0};
+  }
+  // keep within the LDS of a CU and, in place, within 8 points per thread
+  while (s.tb > 1 && (size_t)n * cs * ((s.ip ? 1 : 2) * (size_t)s.tb + 1) > 160 * 1024) s.tb >>= 1;
+  while (s.ip && s.tb > 1 && (size_t)n * s.tb > 8 * (size_t)s.threads) s.tb >>= 1;
+  return s;
 }
 
 template <typename R>
-static size_t smem_for(int n, int TB) {
-  return (size_t)n * sizeof(cpx<R>) * (2 * (size_t)TB + 1);
+static size_t smem_for(int n, int TB, bool ip) {
+  return (size_t)n * sizeof(cpx<R>) * ((ip ? 1 : 2) * (size_t)TB + 1);
 }
 
 #define NEDNER_PASS_LAUNCH(KERNEL, NLEN, GX, GYLINES, IN_T, OUT_T)                                \
   template <typename R>                                                                         \
   static hipError_t run_##KERNEL(const KP& p, const void* in, void* out, hipStream_t s) {        \
     const int n = (NLEN);                                                                       \
-    const int TB = lines_for<R>(n);                                                             \
-    const size_t sh = smem_for<R>(n, TB);                                                       \
-    dim3 grid((GX), ((GYLINES) + TB - 1) / TB);                                                 \
-    hipError_t e = allow_smem(KERNEL<R>, sh);                                                   \
+    const PassShape ps = pass_shape(n, sizeof(cpx<R>));                                         \
+    const int TB = ps.tb;                                                                       \
+    const size_t sh = smem_for<R>(n, TB, ps.ip);                                                \
+    dim3 grid(((GYLINES) + TB - 1) / TB, (GX));                                                 \
+    hipError_t e = ps.ip ? allow_smem(KERNEL<R, true>, sh) : allow_smem(KERNEL<R, false>, sh);  \
     if (e != hipSuccess) return e;                                                              \
-    hipLaunchKernelGGL((KERNEL<R>), grid, dim3(256), sh, s, p, TB,                              \
-                       static_cast<const IN_T*>(in), static_cast<OUT_T*>(out));                 \
+    if (ps.ip)                                                                                  \
+      hipLaunchKernelGGL((KERNEL<R, true>), grid, dim3(ps.threads), sh, s, p, TB,               \
+                         static_cast<const IN_T*>(in), static_cast<OUT_T*>(out));               \
+    else                                                                                        \
+      hipLaunchKernelGGL((KERNEL<R, false>), grid, dim3(ps.threads), sh, s, p, TB,              \
+                         static_cast<const IN_T*>(in), static_cast<OUT_T*>(out));               \
     return hipGetLastError();                                                                   \
   }
 

@@ -78,26 +78,44 @@ __device__ __forceinline__ int pmod(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
-template <int W, int TT, typename R, typename WT, typename A>
-__global__ __launch_bounds__(256) void k_spread(KP p, const R* __restrict__ g, R* __restrict__ U,
-                                                int vec) {
+// Table pointers are separate __restrict__ parameters so that the compiler
+// knows they are read-only for the whole kernel and fetches the wave-uniform
+// ones (list entries, first-axis weights) through the scalar cache.
+// Software pipeline of depth PD: while entry e is accumulated, the samples of
+// entries e+1..e+PD, the first-axis weights of entry e+1 (when they are
+// 4-byte; 8-byte ones are fetched at use) and the index of entry e+PD+1 are
+// already in flight.
+template <int W, int TT, typename R, typename WT, typename A, bool VEC, int PD>
+__device__ __forceinline__ void spread_body(const KP& p, int bx, const int* __restrict__ cellbeg,
+                                            const int* __restrict__ em, const WT* __restrict__ ew,
+                                            const WT* __restrict__ w1t, const R* __restrict__ g,
+                                            R* __restrict__ U) {
+  constexpr bool PW = sizeof(WT) == 4;
   const int lane = threadIdx.x & 63;
-  const int q2 = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  // XCD-aware order: the hardware deals workgroups round-robin to the 8 XCDs;
+  // give each XCD a contiguous run of column groups (of one segment and time
+  // chunk) so that the sensors shared by neighbouring columns stay in its L2.
+  const int ncg = (p.n2 + 3) / 4;
+  const int G = ncg * p.nseg * p.nchunk;
+  const int per = (G + 7) / 8;
+  const int L = (bx & 7) * per + (bx >> 3);
+  if (L >= G) return;
+  const int cgi = L % ncg;
+  const int seg = (L / ncg) % p.nseg;
+  const int chunk = L / (ncg * p.nseg);
+  const int q2 = __builtin_amdgcn_readfirstlane(cgi * 4 + (threadIdx.x >> 6));
   if (q2 >= p.n2) return;
-  const int seg = blockIdx.y;
-  const int chunk = blockIdx.z;
   const int S0 = seg * p.S;
   const int S1 = min(S0 + p.S, p.n1);
   const int Vstart = S0 - W / 2;
   const int Vend = S1 + W / 2 - 2;
-  const int* __restrict__ cb = p.cellbeg + (size_t)(q2 * p.nseg + seg) * p.CB;
-  const int* __restrict__ em = p.ent_m;
-  const WT* __restrict__ ew = static_cast<const WT*>(p.ent_w2);
-  const WT* __restrict__ w1t = static_cast<const WT*>(p.w1);
+  const int* __restrict__ cb = cellbeg + (size_t)(q2 * p.nseg + seg) * p.CB;
   const int Nt = p.Nt;
   const int tb = chunk * 64 * TT + lane * TT;
-  const int valid = Nt - tb;
-  const bool vv = vec != 0;
+  // every lane loads from a valid address; lanes past the end read the first
+  // samples of the row and drop them (Nt is a multiple of TT)
+  const bool lane_ok = tb < Nt;
+  const int toff = lane_ok ? tb : 0;
 
   A acc[W][TT];
 #pragma unroll
@@ -107,14 +125,29 @@ __global__ __launch_bounds__(256) void k_spread(KP p, const R* __restrict__ g, R
 
   int e = cb[0];
   const int eall = cb[Vend - Vstart + 1];
-  // software pipeline: the next entry's data is in flight while this one is used
-  R ng[TT];
-  WT nw2 = WT(0);
-  int nm = 0;
-  if (e < eall) {
-    nm = em[e];
-    nw2 = ew[e];
-    load_tt<TT>(ng, g + (size_t)nm * Nt + tb, valid, vv);
+  auto ld_m = [&](int i) { return i < eall ? em[i] : 0; };
+  auto ld_w2 = [&](int i) { return i < eall ? ew[i] : WT(0); };
+  auto ld_g = [&](R (&v)[TT], int i, int m) {
+    if (i < eall) {
+      load_tt<TT>(v, g + (size_t)m * Nt + toff, TT, VEC);
+    } else {
+#pragma unroll
+      for (int t = 0; t < TT; ++t) v[t] = R(0);
+    }
+  };
+  // pipeline registers
+  R g0[TT], g1[TT];
+  WT w1_cu[W], w1_nx[W];
+  int m1 = ld_m(e + 1), m2 = ld_m(e + 2);
+  WT w2_0 = ld_w2(e), w2_1 = ld_w2(e + 1), w2_2 = ld_w2(e + 2);
+  {
+    const int m0 = ld_m(e);
+    ld_g(g0, e, m0);
+    if constexpr (PD == 2) ld_g(g1, e + 1, m1);
+#pragma unroll
+    for (int k = 0; k < W; ++k) w1_cu[k] = (e < eall) ? w1t[(size_t)m0 * W + k] : WT(0);
+#pragma unroll
+    for (int k = 0; k < W; ++k) w1_nx[k] = WT(0);
   }
   for (int c0 = floor_div(Vstart, W) * W; c0 <= Vend; c0 += W) {
 #pragma unroll
@@ -123,36 +156,65 @@ __global__ __launch_bounds__(256) void k_spread(KP p, const R* __restrict__ g, R
       if (V < Vstart || V > Vend) continue;
       const int stop = cb[V - Vstart + 1];
       while (e < stop) {
-        R cg[TT];
+        // issue: samples of e+PD, weights of e+1, index of e+PD+1
+        R gn[TT];
+        if constexpr (PD == 2)
+          ld_g(gn, e + 2, m2);
+        else
+          ld_g(gn, e + 1, m1);
+        if constexpr (PW) {
+          if (e + 1 < eall) {
 #pragma unroll
-        for (int t = 0; t < TT; ++t) cg[t] = ng[t];
-        const int cm = nm;
-        const WT cw2 = nw2;
-        ++e;
-        if (e < eall) {
-          nm = em[e];
-          nw2 = ew[e];
-          load_tt<TT>(ng, g + (size_t)nm * Nt + tb, valid, vv);
+            for (int k = 0; k < W; ++k) w1_nx[k] = w1t[(size_t)m1 * W + k];
+          }
         }
-        const WT* __restrict__ w1 = w1t + (size_t)cm * W;
+        const int m3 = ld_m(e + 3);
+        const WT w2_3 = ld_w2(e + 3);
+        if constexpr (!PW) {
+          const int m = em[e];
+#pragma unroll
+          for (int k = 0; k < W; ++k) w1_cu[k] = w1t[(size_t)m * W + k];
+        }
+        // accumulate entry e into the ring
         A gw[TT];
 #pragma unroll
-        for (int t = 0; t < TT; ++t) gw[t] = A(cg[t]) * A(cw2);
+        for (int t = 0; t < TT; ++t) gw[t] = A(g0[t]) * A(w2_0);
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          const A wk = A(w1[k]);
+          const A wk = A(w1_cu[k]);
 #pragma unroll
           for (int t = 0; t < TT; ++t) acc[(r + k + W / 2 + 1) % W][t] += wk * gw[t];
         }
+        // rotate the pipeline
+        if constexpr (PD == 2) {
+#pragma unroll
+          for (int t = 0; t < TT; ++t) {
+            g0[t] = g1[t];
+            g1[t] = gn[t];
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < TT; ++t) g0[t] = gn[t];
+        }
+        if constexpr (PW) {
+#pragma unroll
+          for (int k = 0; k < W; ++k) w1_cu[k] = w1_nx[k];
+        }
+        w2_0 = w2_1;
+        w2_1 = w2_2;
+        w2_2 = w2_3;
+        m1 = m2;
+        m2 = m3;
+        ++e;
       }
       // cell row V is done: virtual row V - W/2 + 1 is complete
       const int slot = (r + W / 2 + 1) % W;
       const int Q = V - W / 2 + 1;
-      if (Q >= S0 && Q < S1) {
+      if (Q >= S0 && Q < S1 && lane_ok) {
         R o[TT];
 #pragma unroll
         for (int t = 0; t < TT; ++t) o[t] = R(acc[slot][t]);
-        store_tt<TT>(U + ((size_t)Q * p.n2 + q2) * Nt + tb, o, valid, vv);
+        store_tt<TT>(U + ((size_t)Q * p.n2 + q2) * Nt + tb, o, TT, VEC);
       }
 #pragma unroll
       for (int t = 0; t < TT; ++t) acc[slot][t] = A(0);
@@ -160,16 +222,25 @@ __global__ __launch_bounds__(256) void k_spread(KP p, const R* __restrict__ g, R
   }
 }
 
+template <int W, int TT, typename R, typename WT, typename A, bool VEC, int PD>
+__global__ __launch_bounds__(256) void k_spread(KP p, const int* __restrict__ cellbeg,
+                                                const int* __restrict__ em,
+                                                const WT* __restrict__ ew,
+                                                const WT* __restrict__ w1t,
+                                                const R* __restrict__ g, R* __restrict__ U) {
+  spread_body<W, TT, R, WT, A, VEC, PD>(p, blockIdx.x, cellbeg, em, ew, w1t, g, U);
+}
+
 // Transpose of the spreading: g'[m][n] = sum_taps s_m phi(q1-u1) phi(q2-u2) U'[q1][q2][n].
 // One wavefront per sensor and time chunk; the W x W taps are read straight
 // from the grid (coalesced along time) and summed in a fixed order.
 template <int W, int TT, typename R, typename WT, typename A>
-__global__ __launch_bounds__(256) void k_gather(KP p, const R* __restrict__ U, R* __restrict__ g,
-                                                int vec) {
+__device__ __forceinline__ void gather_body(const KP& p, int bx, int by, const R* __restrict__ U,
+                                            R* __restrict__ g, int vec) {
   const int lane = threadIdx.x & 63;
-  const int m = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int m = __builtin_amdgcn_readfirstlane(bx * 4 + (int)(threadIdx.x >> 6));
   if (m >= p.M) return;
-  const int chunk = blockIdx.y;
+  const int chunk = by;
   const int Nt = p.Nt;
   const int tb = chunk * 64 * TT + lane * TT;
   const int valid = Nt - tb;
@@ -205,14 +276,33 @@ __global__ __launch_bounds__(256) void k_gather(KP p, const R* __restrict__ U, R
   store_tt<TT>(g + (size_t)m * Nt + tb, o, valid, vv);
 }
 
+template <int W, int TT, typename R, typename WT, typename A>
+__global__ __launch_bounds__(256) void k_gather(KP p, const R* __restrict__ U, R* __restrict__ g,
+                                                int vec) {
+  gather_body<W, TT, R, WT, A>(p, blockIdx.x, blockIdx.y, U, g, vec);
+}
+
 // ---------------------------------------------------------------------------
 // dispatch over (precision, W, TT)
 
 template <typename R, typename WT, typename A, int W, int TT>
 static hipError_t spread_wt(const KP& p, const void* g, void* U, int vec, hipStream_t s) {
-  dim3 grid((p.n2 + 3) / 4, p.nseg, p.nchunk);
-  hipLaunchKernelGGL((k_spread<W, TT, R, WT, A>), grid, dim3(256), 0, s,
-                     p, static_cast<const R*>(g), static_cast<R*>(U), vec);
+  const int G = (p.n2 + 3) / 4 * p.nseg * p.nchunk;
+  dim3 grid(8 * ((G + 7) / 8));
+  const int* cb = p.cellbeg;
+  const int* em = p.ent_m;
+  const WT* ew = static_cast<const WT*>(p.ent_w2);
+  const WT* w1 = static_cast<const WT*>(p.w1);
+  const bool deep = p.spread_pd == 2;
+  if (vec && deep)
+    hipLaunchKernelGGL((k_spread<W, TT, R, WT, A, true, 2>), grid, dim3(256), 0, s, p, cb, em, ew, w1,
+                       static_cast<const R*>(g), static_cast<R*>(U));
+  else if (vec)
+    hipLaunchKernelGGL((k_spread<W, TT, R, WT, A, true, 1>), grid, dim3(256), 0, s, p, cb, em, ew, w1,
+                       static_cast<const R*>(g), static_cast<R*>(U));
+  else
+    hipLaunchKernelGGL((k_spread<W, TT, R, WT, A, false, 1>), grid, dim3(256), 0, s, p, cb, em, ew, w1,
+                       static_cast<const R*>(g), static_cast<R*>(U));
   return hipGetLastError();
 }
 
@@ -259,7 +349,9 @@ static int vec_ok(const KP& p, const void* a, const void* b, size_t esz) {
 static hipError_t dispatch(const KP& p, const void* a, void* b, hipStream_t s, bool adj) {
   switch (p.prec) {
     case PREC_FP64: return spread_p<double, double, double>(p, a, b, vec_ok(p, a, b, 8), s, adj);
-    case PREC_FP32C: return spread_p<float, double, double>(p, a, b, vec_ok(p, a, b, 4), s, adj);
+    case PREC_FP32C:
+      return p.wide_w ? spread_p<float, double, double>(p, a, b, vec_ok(p, a, b, 4), s, adj)
+                      : spread_p<float, float, double>(p, a, b, vec_ok(p, a, b, 4), s, adj);
     default: return spread_p<float, float, float>(p, a, b, vec_ok(p, a, b, 4), s, adj);
   }
 }

@@ -29,6 +29,8 @@ struct KP {
   int CB;         // stride of the per-(column, segment) cell offset table: S + W
   int nchunk;     // time chunks of 64*TT samples
   int prec;       // Prec
+  int spread_pd;  // software pipeline depth of the spreading sweep (1 or 2)
+  int wide_w;     // FP32C: 8-byte first-axis weights (fetched at use) instead of 4-byte
 
   // ---- window and frequency constants (double, reduced on the host) -----
   double beta;      // phi(x) = exp(-beta x^2), x in grid units, all three axes
