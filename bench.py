@@ -37,6 +37,8 @@ WORKLOADS = {
     "c3": "65536 sensors 4x denser near the centre, 1024 samples, 30 balls + 5 bead chains -> 256x256x512",
     "c5": "192x192 sensors jittered +/-0.4 pitch, 768 samples, 20 balls + 1% noise -> 192x192x384",
     "c1": "32x32 sensors jittered +/-0.4 pitch, 128 samples, one ball -> 32x32x64",
+    "c4": "64 problems, M ~ U[1024,16384] jittered, Nt in {256,512,1024}, 1-10 balls, s x s x Nt/2, "
+          "one persistent launch per stage",
 }
 
 
@@ -132,6 +134,44 @@ def cpu_baseline(p, leg_limit_s=60.0):
                            "NER by Horner's rule (numpy, one thread), numpy ifftn"))
 
 
+def bench_batch(a, torch, N, synth):
+    """The 64-problem batch: one execute_many per step."""
+    import ctypes
+    probs = synth.batch_c4()
+    kws = [dict(xy=p.xy, h=p.h, nt=p.nt, dt=p.dt, volume=(p.n1, p.n2, p.n3)) for p in probs]
+    bp = N.BatchPlan(kws, precision=a.precision)
+    tune = bp.autotune()
+    dt = torch.float64 if a.precision == "fp64" else torch.float32
+    gs = [torch.as_tensor(p.g, dtype=dt, device=bp.device) for p in probs]
+    outs = [torch.empty((p.n1, p.n2, p.n3), dtype=dt, device=bp.device) for p in probs]
+    for _ in range(a.warmup):
+        bp(gs, outs)
+    torch.cuda.synchronize()
+    N._check(N.lib().nedner_profile_begin(bp._plan, a.steps))
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(a.steps):
+        bp(gs, outs)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / a.steps
+    arr = (ctypes.c_double * 16)()
+    ns = ctypes.c_int(0)
+    names = ctypes.c_char_p()
+    N._check(N.lib().nedner_profile_end(bp._plan, arr, 16, ctypes.byref(ns), ctypes.byref(names)))
+    stages = dict(zip(names.value.decode().split(","), [round(arr[i], 5) for i in range(ns.value)]))
+    points = sum(p.m * p.nt for p in probs)
+    return {"metric": METRIC, "value": round(points / (ms / 1e3) / 1e6, 2), "unit": "Mpts/s",
+            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
+            "config": {"workload": f"c4: {WORKLOADS['c4']}", "problems": len(probs),
+                       "points": points, "precision": a.precision},
+            "volumes_per_s": round(len(probs) * 1e3 / ms, 2), "stages_ms": stages,
+            "autotune": tune, "roofline": None, "cpu_baseline": None}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,7 +181,18 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp32_plain", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     a = ap.parse_args(argv)
+    if a.copy_calibration:
+        import torch
+        x = torch.ones(a.copy_calibration * (1 << 18), dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4, "launches": 3}), flush=True)
+        return 0
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU split of the "
               "operator is a design note, not part of this build", file=sys.stderr)
@@ -153,6 +204,9 @@ def main(argv=None):
     import paper_1501_02946_amd as N
     import synth
 
+    if a.workload == "c4":
+        print(json.dumps(bench_batch(a, torch, N, synth)), flush=True)
+        return 0
     p = synth.config(a.workload)
     plan = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0,
                   precision=a.precision)

@@ -124,6 +124,19 @@ typedef struct {
   int64_t list_entries;          /* (sensor, column) pairs in the spreading lists */
 } nedner_info;
 
+/* Launch shape of a plan: what the autotuner chooses. Accuracy parameters
+   (w, sigma, tau_scale) are never part of it. */
+typedef struct {
+  int32_t rows_per_wave;   /* spreading sweep length (rows of the oversampled grid) */
+  int32_t time_per_lane;   /* spreading time samples per lane: 1, 2 or 4 */
+  int32_t spread_depth;    /* spreading software pipeline depth: 1 or 2 */
+  int32_t pass_lines;      /* FFT passes: lines per workgroup (power of two) */
+  int32_t pass_threads;    /* FFT passes: threads per workgroup (64..512, multiple of 64) */
+  int32_t pass_inplace;    /* FFT passes: in-place (1) or ping-pong (0) transform */
+  double ms_spread;        /* autotune: spreading time of the chosen shape, ms */
+  double ms_execute;       /* autotune: forward execute time of the chosen shape, ms */
+} nedner_tuning;
+
 /* Fill a descriptor with the defaults (w = 12, sigma = 2, tau_scale = 1, FP32). */
 void nedner_desc_init(nedner_desc* desc);
 
@@ -161,6 +174,23 @@ nedner_status nedner_execute_many(nedner_plan plan, const void* const* d_g,
                                   void* const* d_out, int kind, void* stream);
 
 nedner_status nedner_destroy(nedner_plan plan);
+
+/* Current launch shape of a plan (of its first problem for a batch). */
+nedner_status nedner_get_tuning(nedner_plan plan, nedner_tuning* tuning);
+
+/* Apply a launch shape (e.g. one cached from an earlier autotune) to a
+   single-problem plan; rebuilds the spreading lists when the sweep changes.
+   Synchronises the device. Returns NEDNER_E_ARG for an invalid shape. */
+nedner_status nedner_set_tuning(nedner_plan plan, const nedner_tuning* tuning);
+
+/* Measure candidate launch shapes with HIP events on `stream` and keep the
+   fastest: sweep length, time samples per lane and pipeline depth of the
+   spreading (timed alone), then the FFT pass shape (timed on a whole
+   forward execute). `d_g` is one data array of the plan's problem (any
+   values; for a batch, NULL: each problem's spreading is timed on its own
+   workspace slice with the batch's samples per lane kept). Needs the
+   workspace. Synchronises the device; allocates a temporary volume. */
+nedner_status nedner_autotune(nedner_plan plan, const void* d_g, void* stream, nedner_tuning* best);
 
 /* Stage timing with HIP events recorded on the execute stream, for up to
    `max_runs` following executes (forward or adjoint). nedner_profile_end

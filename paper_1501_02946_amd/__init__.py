@@ -19,7 +19,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Plan", "NednerRecon", "NednerAdjoint", "NednerError", "lib", "lsq",
+__all__ = ["Plan", "BatchPlan", "NednerRecon", "NednerAdjoint", "NednerError", "lib", "lsq",
            "power_norm", "PRECISIONS", "KINDS", "FLAGS", "desc_struct", "info_struct",
            "query"]
 
@@ -61,13 +61,21 @@ class info_struct(ctypes.Structure):
                 ("max_abs_theta", ctypes.c_double), ("list_entries", ctypes.c_int64)]
 
 
+class tuning_struct(ctypes.Structure):
+    _fields_ = [("rows_per_wave", ctypes.c_int32), ("time_per_lane", ctypes.c_int32),
+                ("spread_depth", ctypes.c_int32), ("pass_lines", ctypes.c_int32),
+                ("pass_threads", ctypes.c_int32), ("pass_inplace", ctypes.c_int32),
+                ("ms_spread", ctypes.c_double), ("ms_execute", ctypes.c_double)]
+
+
 _LIB = None
 
 EXPORTS = ["nedner_desc_init", "nedner_validate", "nedner_query", "nedner_plan_create",
            "nedner_plan_create_many", "nedner_plan_info", "nedner_workspace_size",
            "nedner_set_workspace", "nedner_execute", "nedner_execute_adjoint",
            "nedner_execute_many", "nedner_destroy", "nedner_status_string",
-           "nedner_last_error", "nedner_version"]
+           "nedner_last_error", "nedner_version", "nedner_profile_begin", "nedner_profile_end",
+           "nedner_get_tuning", "nedner_set_tuning", "nedner_autotune"]
 
 
 def _declare(L):
@@ -91,6 +99,13 @@ def _declare(L):
     L.nedner_last_error.argtypes = []
     L.nedner_last_error.restype = ctypes.c_char_p
     L.nedner_version.argtypes = []
+    L.nedner_profile_begin.argtypes = [vp, i32]
+    L.nedner_profile_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32),
+                                     ctypes.POINTER(ctypes.c_char_p)]
+    T = ctypes.POINTER(tuning_struct)
+    L.nedner_get_tuning.argtypes = [vp, T]
+    L.nedner_set_tuning.argtypes = [vp, T]
+    L.nedner_autotune.argtypes = [vp, vp, vp, T]
     for name in EXPORTS:
         if name not in ("nedner_desc_init", "nedner_status_string", "nedner_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -183,6 +198,7 @@ class Plan:
                              flags=flags, rows_per_wave=rows_per_wave, time_per_lane=time_per_lane)
         self.m, self.nt, self.volume = int(d.m), int(nt), (n1, n2, n3)
         self.precision = precision
+        self._w, self._sigma = int(w), float(sigma)
         self.dtype = torch.float64 if d.prec == 0 else torch.float32
         self._plan = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -270,6 +286,154 @@ class Plan:
             _check(lib().nedner_execute_adjoint(self._plan, ctypes.c_void_p(v.data_ptr()), k,
                                                 ctypes.c_void_p(out.data_ptr()), self._stream()))
         return out
+
+    # -- launch shape -------------------------------------------------------
+    @property
+    def tuning(self) -> dict:
+        t = tuning_struct()
+        _check(lib().nedner_get_tuning(self._plan, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in tuning_struct._fields_}
+
+    def set_tuning(self, tuning: dict):
+        t = tuning_struct(**{k: tuning[k] for k, _ in tuning_struct._fields_ if k in tuning})
+        with self._torch.cuda.device(self.device):
+            _check(lib().nedner_set_tuning(self._plan, ctypes.byref(t)))
+        self._refresh_info()
+
+    def _refresh_info(self):
+        info = info_struct()
+        _check(lib().nedner_plan_info(self._plan, ctypes.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in info_struct._fields_ if k != "pad0"}
+
+    def cache_key(self) -> str:
+        arch = self._torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        n1, n2, n3 = self.volume
+        return f"{arch}|{self.precision}|m{self.m}|nt{self.nt}|{n1}x{n2}x{n3}|w{self._w}|s{self._sigma}"
+
+    def autotune(self, g=None, cache: str | None = None) -> dict:
+        """Pick the fastest launch shape (sweep length, samples per lane, pass
+        shape) by timing candidates on the GPU; results are cached in a JSON
+        file keyed by device, precision and problem size (NEDNER_TUNING_CACHE
+        or ~/.cache/nedner/tuning.json)."""
+        import json
+        path = cache or os.environ.get("NEDNER_TUNING_CACHE",
+                                       os.path.join(os.path.expanduser("~"), ".cache", "nedner",
+                                                    "tuning.json"))
+        key = self.cache_key()
+        table = {}
+        if os.path.exists(path):
+            try:
+                with open(path) as fh:
+                    table = json.load(fh)
+            except (OSError, ValueError):
+                table = {}
+        if key in table:
+            self.set_tuning(table[key])
+            return table[key]
+        torch = self._torch
+        if g is None:
+            g = torch.zeros((self.m, self.nt), dtype=self.dtype, device=self.device)
+        g = self._check_in(g, (self.m, self.nt), "g")
+        self._workspace()
+        t = tuning_struct()
+        with torch.cuda.device(self.device):
+            _check(lib().nedner_autotune(self._plan, ctypes.c_void_p(g.data_ptr()), self._stream(),
+                                         ctypes.byref(t)))
+        self._refresh_info()
+        res = {k: getattr(t, k) for k, _ in tuning_struct._fields_}
+        table[key] = res
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+        except OSError:
+            pass
+        return res
+
+    def close(self):
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            lib().nedner_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchPlan:
+    """Many independent reconstructions run together: one persistent launch
+    per pipeline stage for the whole batch (uneven sensor counts, lengths and
+    grids are allowed; precision and window width are shared).
+
+    `problems` is a sequence of dicts with the keyword arguments of Plan
+    (xy, nt, dt, volume, and optionally c, h, t0, a1, a2, d1, d2, d3).
+    """
+
+    def __init__(self, problems, precision="fp32c", w=12, sigma=2.0, tau_scale=1.0, flags=0,
+                 time_per_lane=0, device=None):
+        import torch
+        self._torch = torch
+        if not torch.cuda.is_available():
+            raise NednerError(5, "no GPU: the NEDNER library runs on MI355X only")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else int(device))
+        descs = (desc_struct * len(problems))()
+        keep = []
+        self.shapes = []
+        for i, pr in enumerate(problems):
+            pr = dict(pr)
+            n1, n2, n3 = (int(v) for v in pr.pop("volume"))
+            d, k = _make_desc(pr.pop("xy"), pr.pop("h", None), pr.pop("nt"), pr.pop("dt"), n1, n2, n3,
+                              precision=precision, w=w, sigma=sigma, tau_scale=tau_scale, flags=flags,
+                              time_per_lane=time_per_lane, **pr)
+            descs[i] = d
+            keep.append(k)
+            self.shapes.append(((int(d.m), int(d.nt)), (n1, n2, n3)))
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.precision = precision
+        self._plan = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().nedner_plan_create_many(descs, len(problems), self.device.index, None,
+                                                 ctypes.byref(self._plan)))
+        del keep
+        info = info_struct()
+        _check(lib().nedner_plan_info(self._plan, ctypes.byref(info)))
+        self.workspace_bytes = int(info.workspace_bytes)
+        self._ws = self._torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8,
+                                     device=self.device)
+        _check(lib().nedner_set_workspace(self._plan, ctypes.c_void_p(self._ws.data_ptr()),
+                                          ctypes.c_size_t(self._ws.numel())))
+
+    def forward(self, gs, outs=None):
+        """Data tensors [(M_i, Nt_i)] -> volumes [(N1_i, N2_i, N3_i)]."""
+        torch = self._torch
+        if len(gs) != len(self.shapes):
+            raise ValueError("one data tensor per problem")
+        ins = []
+        for g, (gshape, _) in zip(gs, self.shapes):
+            if g.device != self.device or g.dtype != self.dtype or tuple(g.shape) != gshape:
+                raise ValueError(f"data must be {self.dtype} {gshape} on {self.device}")
+            ins.append(g.contiguous())
+        if outs is None:
+            outs = [torch.empty(vs, dtype=self.dtype, device=self.device) for _, vs in self.shapes]
+        n = len(ins)
+        gp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in ins])
+        op = (ctypes.c_void_p * n)(*[t.data_ptr() for t in outs])
+        with torch.cuda.device(self.device):
+            stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            _check(lib().nedner_execute_many(self._plan, gp, op, KINDS["volume"], stream))
+        return outs
+
+    __call__ = forward
+
+    def autotune(self) -> dict:
+        """Choose every problem's spreading sweep length by timing it alone."""
+        t = tuning_struct()
+        with self._torch.cuda.device(self.device):
+            stream = ctypes.c_void_p(self._torch.cuda.current_stream(self.device).cuda_stream)
+            _check(lib().nedner_autotune(self._plan, None, stream, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in tuning_struct._fields_}
 
     def close(self):
         if getattr(self, "_plan", None) is not None and self._plan.value:

@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "kparams.hpp"
+#include "batch.hpp"
 #include "nedner.h"
 
 using nedner::KP;
@@ -375,6 +375,21 @@ struct nedner_plan_s {
   size_t need_ws = 0;
   size_t off1 = 0;
   std::vector<nedner_plan_s*> subs;  // batched plans
+  // batched plan state (subs non-empty)
+  nedner::BatchProb* d_bp = nullptr;       // device problem table
+  int2* d_items = nullptr;                 // work lists of all stages, concatenated
+  int* d_counters = nullptr;               // one queue head per stage
+  int stage_off[nedner::ST_COUNT] = {};    // offset of each stage's list in d_items
+  int stage_total[nedner::ST_COUNT] = {};
+  size_t pass_smem[nedner::ST_COUNT] = {};
+  size_t col_smem = 0;
+  int col_cpw = 1;
+  KP kp0{};                                // uniform launch parameters of the batch
+  std::vector<size_t> sub_off;             // workspace slice of each problem
+  void* d_items_alloc = nullptr;           // current work-list allocation (also in d_items)
+  // host copies of the geometry, to rebuild the spreading lists for a new shape
+  std::vector<double> hxy, hh;
+  std::vector<void*> list_allocs;          // device spreading lists (replaced on reshaping)
   // stage profiling
   std::vector<hipEvent_t> ev;
   int prof_max = 0, prof_runs = 0, prof_stages = 0;
@@ -419,6 +434,13 @@ class DeviceGuard {
   int old_ = 0;
   bool ok_ = false;
 };
+
+void destroy_one(nedner_plan p);
+nedner_status batch_upload_table(nedner_plan bp);
+nedner_status forward_impl(nedner_plan plan, const void* d_g, void* d_out, int kind, hipStream_t s);
+nedner_status batch_build_lists(nedner_plan bp);
+size_t stage_blocks(const KP& k, int stage, int cpw);
+size_t pass_lds(const KP& k, int stage);
 
 nedner_status hip_fail(nedner_plan p, hipError_t e, const char* where) {
   if (p) p->broken = true;
@@ -496,6 +518,21 @@ nedner_status create_one(const nedner_desc* desc, int device, nedner_plan* out) 
   for (int64_t n = 0; n < desc->nt; ++n) dtb[n] = 1.0 / phihat(v.beta, double(n - desc->nt / 2), double(v.ntt));
 
   DevAlloc A;
+  // FFT pass shape: 16 lines (whole 128-byte rows of float pairs), 512
+  // threads, in place (measured best on the 128^2 x 512 and 256^2 x 1024
+  // workloads); NEDNER_PASS_SHAPE="lines,threads,inplace" overrides it
+  k.pass_lines = 16;
+  k.pass_threads = 512;
+  k.pass_ip = 1;
+  if (const char* e = getenv("NEDNER_PASS_SHAPE")) {
+    int a = 0, b = 0, c = 0;
+    if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a > 0 && (a & (a - 1)) == 0 && b >= 64 && b <= 512 &&
+        b % 64 == 0) {
+      k.pass_lines = a;
+      k.pass_threads = b;
+      k.pass_ip = c != 0;
+    }
+  }
   const SpreadOpt so = spread_opt();
   k.spread_pd = so.pd;
   k.wide_w = desc->prec == NEDNER_FP32_COMPENSATED && so.wide;
@@ -503,10 +540,17 @@ nedner_status create_one(const nedner_desc* desc, int device, nedner_plan* out) 
   const bool dbl = desc->prec == NEDNER_FP64;
   k.w1 = wide ? A.upload(G.w1) : A.upload_as<float>(G.w1);
   k.w2 = wide ? A.upload(G.w2) : A.upload_as<float>(G.w2);
-  k.ent_w2 = wide ? A.upload(G.ent_w2) : A.upload_as<float>(G.ent_w2);
   k.cell = static_cast<const int*>(A.upload(G.cell));
-  k.ent_m = static_cast<const int*>(A.upload(G.ent_m));
-  k.cellbeg = static_cast<const int*>(A.upload(G.cellbeg));
+  {
+    DevAlloc Lst;
+    k.ent_w2 = wide ? Lst.upload(G.ent_w2) : Lst.upload_as<float>(G.ent_w2);
+    k.ent_m = static_cast<const int*>(Lst.upload(G.ent_m));
+    k.cellbeg = static_cast<const int*>(Lst.upload(G.cellbeg));
+    p->list_allocs = Lst.ptrs;
+    if (Lst.err != hipSuccess && A.err == hipSuccess) A.err = Lst.err;
+  }
+  p->hxy.assign(desc->xy, desc->xy + 2 * desc->m);
+  if (desc->h) p->hh.assign(desc->h, desc->h + desc->m);
   k.dec1 = dbl ? A.upload(d1) : A.upload_as<float>(d1);
   k.dec2 = dbl ? A.upload(d2) : A.upload_as<float>(d2);
   k.dect = dbl ? A.upload(dtb) : A.upload_as<float>(dtb);
@@ -529,6 +573,7 @@ nedner_status create_one(const nedner_desc* desc, int device, nedner_plan* out) 
   if (A.err != hipSuccess) {
     const hipError_t e = A.err;
     for (void* q : p->allocs) (void)hipFree(q);
+    for (void* q : p->list_allocs) (void)hipFree(q);
     delete p;
     if (e == hipErrorOutOfMemory) return fail(NEDNER_E_OOM, "device allocation of plan tables failed");
     return fail(NEDNER_E_HIP, std::string("plan upload: ") + hipGetErrorString(e));
@@ -642,6 +687,417 @@ nedner_status adjoint_impl(nedner_plan plan, const void* d_in, int kind, void* d
   return NEDNER_OK;
 }
 
+// ---------------------------------------------------------------- batches
+
+size_t stage_blocks(const KP& k, int stage, int cpw) {
+  auto ceil_div = [](long a, long b) { return (a + b - 1) / b; };
+  const int cs = k.prec == NEDNER_FP64 ? 16 : 8;
+  switch (stage) {
+    case nedner::ST_SPREAD: {
+      const long G = ceil_div(k.n2, 4) * k.nseg * k.nchunk;
+      return size_t(8 * ceil_div(G, 8));
+    }
+    case nedner::ST_LAT_A: return size_t(ceil_div(k.Nt / 2, nedner::pass_lines_for(k, k.n2, cs)) * k.n1);
+    case nedner::ST_LAT_B: return size_t(ceil_div(k.Nt, nedner::pass_lines_for(k, k.n1, cs)) * k.K2);
+    case nedner::ST_COLUMN: return size_t(ceil_div((long)k.J1 * k.K2, cpw));
+    case nedner::ST_PASS_C: return size_t(ceil_div(k.N3, nedner::pass_lines_for(k, k.N1, cs)) * k.K2);
+    default: return size_t(ceil_div(k.N3 / 2, nedner::pass_lines_for(k, k.N2, cs)) * k.N1);
+  }
+}
+
+size_t pass_lds(const KP& k, int stage) {
+  const int cs = k.prec == NEDNER_FP64 ? 16 : 8;
+  int n = 0;
+  switch (stage) {
+    case nedner::ST_LAT_A: n = k.n2; break;
+    case nedner::ST_LAT_B: n = k.n1; break;
+    case nedner::ST_PASS_C: n = k.N1; break;
+    case nedner::ST_PASS_D: n = k.N2; break;
+    default: return 0;
+  }
+  const int tb = nedner::pass_lines_for(k, n, cs);
+  return (size_t)n * cs * ((k.pass_ip ? 1 : 2) * (size_t)tb + 1);
+}
+
+nedner_status create_batch(const nedner_desc* descs, int count, int device, nedner_plan* out) {
+  if (!descs || count < 1 || count > 4096) return fail(NEDNER_E_ARG, "count must be in [1, 4096]");
+  const int prec = descs[0].prec, w = descs[0].w;
+  bool all4 = true;
+  for (int i = 0; i < count; ++i) {
+    if (descs[i].prec != prec || descs[i].w != w)
+      return fail(NEDNER_E_ARG, "all problems of a batch must share precision and window width");
+    if (descs[i].nt % 4) all4 = false;
+  }
+  // the spreading kernel's time-per-lane is a compile-time shape: one for the batch
+  int TT = descs[0].time_per_lane;
+  if (TT == 0) TT = all4 ? 4 : 2;
+  nedner_plan bp = new (std::nothrow) nedner_plan_s();
+  if (!bp) return fail(NEDNER_E_OOM, "host allocation failed");
+  bp->device = device;
+  for (int i = 0; i < count; ++i) {
+    nedner_desc d = descs[i];
+    d.time_per_lane = TT;
+    nedner_plan sp = nullptr;
+    nedner_status st = create_one(&d, device, &sp);
+    if (st != NEDNER_OK) {
+      const std::string msg = "problem " + std::to_string(i) + ": " + g_last_error;
+      destroy_one(bp);
+      return fail(st, msg);
+    }
+    bp->subs.push_back(sp);
+  }
+  // uniform launch parameters; the largest per-column transform sets the register bound
+  bp->kp0 = bp->subs[0]->kp;
+  size_t wave_max = 0, shared_max = 0;
+  for (auto* sp : bp->subs) {
+    bp->kp0.ntt = std::max(bp->kp0.ntt, sp->kp.ntt);
+    bp->kp0.N3 = std::max(bp->kp0.N3, sp->kp.N3);
+    wave_max = std::max(wave_max, nedner::column_wave_bytes_host(sp->kp));
+    shared_max = std::max(shared_max, nedner::column_shared_bytes_host(sp->kp));
+  }
+  int best = 1;
+  size_t best_waves = 0;
+  for (int cw = 1; cw <= 8; ++cw) {
+    const size_t wg = shared_max + cw * wave_max;
+    if (wg > 160 * 1024) break;
+    const size_t waves = cw * ((160 * 1024) / wg);
+    if (waves > best_waves) {
+      best_waves = waves;
+      best = cw;
+    }
+  }
+  bp->col_cpw = best;
+  bp->col_smem = shared_max + best * wave_max;
+  // workspace slices
+  size_t off = 0;
+  for (auto* sp : bp->subs) {
+    bp->sub_off.push_back(off);
+    off += align256(sp->need_ws);
+  }
+  bp->need_ws = std::max<size_t>(off, 256);
+  DeviceGuard guard(device);
+  {
+    nedner_status ls = batch_build_lists(bp);
+    if (ls != NEDNER_OK) {
+      const std::string msg = g_last_error;
+      destroy_one(bp);
+      return fail(ls, msg);
+    }
+  }
+  DevAlloc A;
+  std::vector<int> zeros(nedner::ST_COUNT, 0);
+  bp->d_counters = static_cast<int*>(const_cast<void*>(A.upload(zeros)));
+  if (A.err == hipSuccess) {
+    void* q = nullptr;
+    A.err = hipMalloc(&q, sizeof(nedner::BatchProb) * count);
+    if (A.err == hipSuccess) A.ptrs.push_back(q);
+    bp->d_bp = static_cast<nedner::BatchProb*>(q);
+  }
+  bp->allocs.insert(bp->allocs.end(), A.ptrs.begin(), A.ptrs.end());
+  if (A.err != hipSuccess) {
+    const hipError_t e = A.err;
+    destroy_one(bp);
+    return fail(e == hipErrorOutOfMemory ? NEDNER_E_OOM : NEDNER_E_HIP,
+                std::string("batch tables: ") + hipGetErrorString(e));
+  }
+  bp->info = bp->subs[0]->info;
+  bp->info.workspace_bytes = bp->need_ws;
+  *out = bp;
+  return NEDNER_OK;
+}
+
+// Write the problem table (kernel parameters and workspace slices) to the device.
+nedner_status batch_upload_table(nedner_plan bp) {
+  std::vector<nedner::BatchProb> t(bp->subs.size());
+  char* ws = static_cast<char*>(bp->ws);
+  for (size_t i = 0; i < t.size(); ++i) {
+    t[i].kp = bp->subs[i]->kp;
+    t[i].g = nullptr;
+    t[i].out = nullptr;
+    t[i].b0 = ws + bp->sub_off[i];
+    t[i].b1 = ws + bp->sub_off[i] + bp->subs[i]->off1;
+  }
+  DeviceGuard guard(bp->device);
+  const hipError_t e = hipMemcpy(bp->d_bp, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(bp, e, "batch table upload");
+  return NEDNER_OK;
+}
+
+nedner_status execute_many_impl(nedner_plan plan, const void* const* d_g, void* const* d_out, hipStream_t s) {
+  const int count = int(plan->subs.size());
+  bool vec = true;
+  for (int i = 0; i < count; ++i) {
+    if (!d_g[i] || !d_out[i]) return fail(NEDNER_E_ARG, "NULL device pointer for problem " + std::to_string(i));
+    const size_t al = (size_t)plan->kp0.TT * (plan->kp0.prec == NEDNER_FP64 ? 8 : 4);
+    if (reinterpret_cast<uintptr_t>(d_g[i]) % al) vec = false;
+  }
+  Marks mk(plan, s, 6, kFwdNames);
+  for (int first = 0; first < count; first += 64) {
+    nedner::PtrChunk ch{};
+    ch.first = first;
+    ch.n = std::min(64, count - first);
+    for (int i = 0; i < ch.n; ++i) {
+      ch.g[i] = d_g[first + i];
+      ch.out[i] = d_out[first + i];
+    }
+    NEDNER_RUN(nedner::launch_batch_prepare(plan->d_bp, ch, plan->d_counters, first == 0 ? nedner::ST_COUNT : 0, s),
+               "batch prepare");
+  }
+  auto wl = [&](int st) {
+    return nedner::WorkList{plan->d_items + plan->stage_off[st], plan->stage_total[st], plan->d_counters + st};
+  };
+  const KP& k0 = plan->kp0;
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_spread_many(k0, plan->d_bp, wl(nedner::ST_SPREAD), vec, s), "batched spread");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_pass_many(k0, nedner::ST_LAT_A, plan->d_bp, wl(nedner::ST_LAT_A),
+                                      plan->pass_smem[nedner::ST_LAT_A], s), "batched lateral FFT");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_pass_many(k0, nedner::ST_LAT_B, plan->d_bp, wl(nedner::ST_LAT_B),
+                                      plan->pass_smem[nedner::ST_LAT_B], s), "batched lateral FFT");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_column_many(k0, plan->d_bp, wl(nedner::ST_COLUMN), plan->col_cpw, plan->col_smem, s),
+             "batched NER column");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_pass_many(k0, nedner::ST_PASS_C, plan->d_bp, wl(nedner::ST_PASS_C),
+                                      plan->pass_smem[nedner::ST_PASS_C], s), "batched inverse FFT");
+  NEDNER_RUN(mk.mark(), "event");
+  NEDNER_RUN(nedner::launch_pass_many(k0, nedner::ST_PASS_D, plan->d_bp, wl(nedner::ST_PASS_D),
+                                      plan->pass_smem[nedner::ST_PASS_D], s), "batched inverse FFT");
+  NEDNER_RUN(mk.mark(), "event");
+  return NEDNER_OK;
+}
+
+// ---------------------------------------------------------------- reshaping and tuning
+
+// Rebuild the spreading lists of a single-problem plan for sweeps of S rows,
+// TT samples per lane and pipeline depth PD. Weights and workspace do not change.
+nedner_status set_spread_shape(nedner_plan p, int S, int TT, int PD) {
+  nedner_desc d = p->desc;
+  d.xy = p->hxy.data();
+  d.h = p->hh.empty() ? nullptr : p->hh.data();
+  d.rows_per_wave = S;
+  d.time_per_lane = TT;
+  Derived v;
+  nedner_status st = validate_impl(&d, &v);
+  if (st != NEDNER_OK) return st;
+  Geometry G;
+  try {
+    build_geometry(d, v, G);
+  } catch (const std::bad_alloc&) {
+    return fail(NEDNER_E_OOM, "host allocation failed while building the spreading lists");
+  }
+  DeviceGuard guard(p->device);
+  DevAlloc L;
+  const bool wide = p->kp.prec == NEDNER_FP64 || p->kp.wide_w;
+  const void* ew = wide ? L.upload(G.ent_w2) : L.upload_as<float>(G.ent_w2);
+  const void* em = L.upload(G.ent_m);
+  const void* cb = L.upload(G.cellbeg);
+  if (L.err != hipSuccess) {
+    for (void* q : L.ptrs) (void)hipFree(q);
+    return fail(L.err == hipErrorOutOfMemory ? NEDNER_E_OOM : NEDNER_E_HIP,
+                std::string("spreading list upload: ") + hipGetErrorString(L.err));
+  }
+  for (void* q : p->list_allocs) (void)hipFree(q);
+  p->list_allocs = L.ptrs;
+  KP& k = p->kp;
+  k.ent_w2 = ew;
+  k.ent_m = static_cast<const int*>(em);
+  k.cellbeg = static_cast<const int*>(cb);
+  k.TT = v.TT;
+  k.S = v.S;
+  k.nseg = v.nseg;
+  k.CB = v.CB;
+  k.nchunk = v.nchunk;
+  k.spread_pd = PD;
+  p->v = v;
+  p->desc.rows_per_wave = S;
+  p->desc.time_per_lane = TT;
+  p->info.segments = v.nseg;
+  p->info.rows_per_wave = v.S;
+  p->info.time_per_lane = v.TT;
+  p->info.list_entries = int64_t(G.ent_m.size());
+  return NEDNER_OK;
+}
+
+// Work lists of a batch: per stage, the problems in decreasing order of
+// their block count, each problem's blocks consecutive.
+nedner_status batch_build_lists(nedner_plan bp) {
+  std::vector<int2> items;
+  const int count = int(bp->subs.size());
+  for (int st = 0; st < nedner::ST_COUNT; ++st) {
+    std::vector<std::pair<size_t, int>> order;
+    size_t lds = 0;
+    for (int i = 0; i < count; ++i) {
+      order.push_back({stage_blocks(bp->subs[i]->kp, st, bp->col_cpw), i});
+      lds = std::max(lds, pass_lds(bp->subs[i]->kp, st));
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<size_t, int>& a, const std::pair<size_t, int>& b) { return a.first > b.first; });
+    bp->stage_off[st] = int(items.size());
+    for (auto& o : order)
+      for (size_t b = 0; b < o.first; ++b) items.push_back(make_int2(o.second, int(b)));
+    bp->stage_total[st] = int(items.size()) - bp->stage_off[st];
+    bp->pass_smem[st] = lds;
+  }
+  DeviceGuard guard(bp->device);
+  DevAlloc A;
+  void* it = const_cast<void*>(A.upload(items));
+  if (A.err != hipSuccess) {
+    for (void* q : A.ptrs) (void)hipFree(q);
+    return fail(NEDNER_E_OOM, std::string("work list upload: ") + hipGetErrorString(A.err));
+  }
+  if (bp->d_items_alloc) {
+    (void)hipFree(bp->d_items_alloc);
+    bp->allocs.erase(std::remove(bp->allocs.begin(), bp->allocs.end(), bp->d_items_alloc), bp->allocs.end());
+  }
+  bp->d_items_alloc = it;
+  bp->allocs.push_back(it);
+  bp->d_items = static_cast<int2*>(it);
+  return NEDNER_OK;
+}
+
+void get_tuning(nedner_plan p, nedner_tuning* t) {
+  std::memset(t, 0, sizeof(*t));
+  t->rows_per_wave = p->kp.S;
+  t->time_per_lane = p->kp.TT;
+  t->spread_depth = p->kp.spread_pd;
+  t->pass_lines = p->kp.pass_lines;
+  t->pass_threads = p->kp.pass_threads;
+  t->pass_inplace = p->kp.pass_ip;
+}
+
+bool pass_shape_ok(int lines, int threads) {
+  return lines > 0 && (lines & (lines - 1)) == 0 && lines <= 64 && threads >= 64 && threads <= 512 &&
+         threads % 64 == 0;
+}
+
+// Mean milliseconds of `reps` forward executes of `kind` after one warm-up.
+nedner_status time_forward(nedner_plan p, const void* d_g, void* d_out, int kind, hipStream_t s, int reps,
+                           double* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return fail(NEDNER_E_HIP, "hipEventCreate failed");
+  }
+  nedner_status st = forward_impl(p, d_g, d_out, kind, s);
+  if (st == NEDNER_OK && hipEventRecord(a, s) != hipSuccess) st = fail(NEDNER_E_HIP, "hipEventRecord failed");
+  for (int r = 0; r < reps && st == NEDNER_OK; ++r) st = forward_impl(p, d_g, d_out, kind, s);
+  float t = 0.f;
+  if (st == NEDNER_OK && (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                          hipEventElapsedTime(&t, a, b) != hipSuccess))
+    st = fail(NEDNER_E_HIP, "event timing failed");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = t / reps;
+  return st;
+}
+
+// Spreading shape search of one problem; U is a buffer of the spread grid's size.
+nedner_status tune_spread(nedner_plan p, const void* d_g, void* U, hipStream_t s, int fixed_tt, double* best_ms) {
+  const int n1 = p->kp.n1, W = p->kp.W, Nt = p->kp.Nt;
+  std::vector<int> tts;
+  if (fixed_tt)
+    tts.push_back(fixed_tt);
+  else
+    for (int tt : {4, 2, 1})
+      if (Nt % tt == 0 && (tt == 1 || Nt >= 32 * tt)) tts.push_back(tt);
+  std::vector<int> ss;
+  for (int S : {24, 32, 48, 64, 96})
+    if (S <= n1 && S >= W) ss.push_back(S);
+  if (ss.empty()) ss.push_back(n1);
+  int bS = p->kp.S, bT = p->kp.TT, bP = p->kp.spread_pd;
+  double best = 1e300;
+  for (int tt : tts)
+    for (int S : ss)
+      for (int pd : {1, 2}) {
+        nedner_status st = set_spread_shape(p, S, tt, pd);
+        if (st != NEDNER_OK) return st;
+        double ms = 0;
+        st = time_forward(p, d_g, U, NEDNER_STAGE_GRID, s, 3, &ms);
+        if (st != NEDNER_OK) return st;
+        if (ms < best) {
+          best = ms;
+          bS = S;
+          bT = tt;
+          bP = pd;
+        }
+      }
+  *best_ms = best;
+  return set_spread_shape(p, bS, bT, bP);
+}
+
+nedner_status autotune_single(nedner_plan p, const void* d_g, hipStream_t s, nedner_tuning* out) {
+  if (!p->ws || p->ws_bytes < p->need_ws) return fail(NEDNER_E_WORKSPACE, "autotune needs the workspace");
+  if (!d_g) return fail(NEDNER_E_ARG, "autotune needs a data array");
+  double ms_spread = 0;
+  nedner_status st = tune_spread(p, d_g, p->ws, s, 0, &ms_spread);
+  if (st != NEDNER_OK) return st;
+  void* vol = nullptr;
+  const size_t vb = (size_t)p->kp.N1 * p->kp.N2 * p->kp.N3 * (p->kp.prec == NEDNER_FP64 ? 8 : 4);
+  if (hipMalloc(&vol, vb) != hipSuccess) return fail(NEDNER_E_OOM, "autotune: no memory for a volume");
+  const int cand[][3] = {{16, 512, 1}, {8, 512, 1}, {16, 256, 1}, {8, 256, 1}, {16, 256, 0}, {8, 256, 0}, {16, 512, 0}};
+  KP& k = p->kp;
+  int bl = k.pass_lines, bt = k.pass_threads, bi = k.pass_ip;
+  double best = 1e300;
+  for (auto& c : cand) {
+    k.pass_lines = c[0];
+    k.pass_threads = c[1];
+    k.pass_ip = c[2];
+    double ms = 0;
+    st = time_forward(p, d_g, vol, NEDNER_VOLUME_REAL, s, 3, &ms);
+    if (st != NEDNER_OK) break;
+    if (ms < best) {
+      best = ms;
+      bl = c[0];
+      bt = c[1];
+      bi = c[2];
+    }
+  }
+  (void)hipFree(vol);
+  k.pass_lines = bl;
+  k.pass_threads = bt;
+  k.pass_ip = bi;
+  if (st != NEDNER_OK) return st;
+  if (out) {
+    get_tuning(p, out);
+    out->ms_spread = ms_spread;
+    out->ms_execute = best;
+  }
+  return NEDNER_OK;
+}
+
+nedner_status autotune_batch(nedner_plan bp, hipStream_t s, nedner_tuning* out) {
+  if (!bp->ws || bp->ws_bytes < bp->need_ws) return fail(NEDNER_E_WORKSPACE, "autotune needs the workspace");
+  double total = 0;
+  for (size_t i = 0; i < bp->subs.size(); ++i) {
+    nedner_plan sp = bp->subs[i];
+    char* slice = static_cast<char*>(bp->ws) + bp->sub_off[i];
+    // the problem's data is not at hand: time the spreading on zeros in the
+    // second buffer of its slice (the cost does not depend on the values)
+    const size_t gbytes = (size_t)sp->kp.M * sp->kp.Nt * (sp->kp.prec == NEDNER_FP64 ? 8 : 4);
+    char* gz = slice + sp->off1;
+    if (gbytes > sp->need_ws - sp->off1) return fail(NEDNER_E_UNSUPPORTED, "problem data larger than its buffer");
+    if (hipMemsetAsync(gz, 0, gbytes, s) != hipSuccess) return fail(NEDNER_E_HIP, "hipMemsetAsync failed");
+    double ms = 0;
+    nedner_status st = tune_spread(sp, gz, slice, s, bp->kp0.TT, &ms);
+    if (st != NEDNER_OK) return st;
+    total += ms;
+  }
+  bp->kp0.spread_pd = bp->subs[0]->kp.spread_pd;
+  for (auto* sp : bp->subs) sp->kp.spread_pd = bp->kp0.spread_pd;
+  nedner_status st = batch_build_lists(bp);
+  if (st != NEDNER_OK) return st;
+  st = batch_upload_table(bp);
+  if (st != NEDNER_OK) return st;
+  if (out) {
+    get_tuning(bp->subs[0], out);
+    out->ms_spread = total;
+    out->ms_execute = 0;
+  }
+  return NEDNER_OK;
+}
+
 void free_events(nedner_plan p) {
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   p->ev.clear();
@@ -651,10 +1107,11 @@ void free_events(nedner_plan p) {
 void destroy_one(nedner_plan p) {
   if (!p) return;
   for (auto* s : p->subs) destroy_one(s);
-  if (!p->allocs.empty() || !p->ev.empty()) {
+  if (!p->allocs.empty() || !p->ev.empty() || !p->list_allocs.empty()) {
     DeviceGuard guard(p->device);
     free_events(p);
     for (void* q : p->allocs) (void)hipFree(q);
+    for (void* q : p->list_allocs) (void)hipFree(q);
   }
   delete p;
 }
@@ -702,12 +1159,10 @@ nedner_status nedner_plan_create(const nedner_desc* desc, int device, void* stre
 
 nedner_status nedner_plan_create_many(const nedner_desc* descs, int count, int device, void* stream,
                                       nedner_plan* plan) {
-  (void)descs;
-  (void)count;
-  (void)device;
   (void)stream;
-  if (plan) *plan = nullptr;
-  return fail(NEDNER_E_UNSUPPORTED, "batched plans are not available in this build");
+  if (!plan) return fail(NEDNER_E_ARG, "plan output pointer is NULL");
+  *plan = nullptr;
+  return create_batch(descs, count, device, plan);
 }
 
 nedner_status nedner_plan_info(nedner_plan plan, nedner_info* info) {
@@ -731,6 +1186,7 @@ nedner_status nedner_set_workspace(nedner_plan plan, void* d_ws, size_t bytes) {
                                         std::to_string(plan->need_ws));
   plan->ws = d_ws;
   plan->ws_bytes = d_ws ? bytes : 0;
+  if (!plan->subs.empty() && d_ws) return batch_upload_table(plan);
   return NEDNER_OK;
 }
 
@@ -754,12 +1210,16 @@ nedner_status nedner_execute_adjoint(nedner_plan plan, const void* d_in, int kin
 
 nedner_status nedner_execute_many(nedner_plan plan, const void* const* d_g, void* const* d_out, int kind,
                                   void* stream) {
-  (void)d_g;
-  (void)d_out;
-  (void)kind;
-  (void)stream;
   if (!plan) return fail(NEDNER_E_ARG, "plan is NULL");
-  return fail(NEDNER_E_UNSUPPORTED, "batched plans are not available in this build");
+  if (plan->subs.empty()) return fail(NEDNER_E_ARG, "not a batched plan: use nedner_execute");
+  if (plan->broken) return fail(NEDNER_E_STATE, "plan is unusable after an earlier HIP error");
+  if (kind != NEDNER_VOLUME_REAL) return fail(NEDNER_E_UNSUPPORTED, "batched execution produces volumes only");
+  if (!d_g || !d_out) return fail(NEDNER_E_ARG, "NULL pointer array");
+  if (!plan->ws || plan->ws_bytes < plan->need_ws)
+    return fail(NEDNER_E_WORKSPACE, "no workspace, or one smaller than nedner_workspace_size");
+  DeviceGuard guard(plan->device);
+  if (!guard.ok()) return fail(NEDNER_E_HIP, "cannot select the plan's device");
+  return execute_many_impl(plan, d_g, d_out, static_cast<hipStream_t>(stream));
 }
 
 nedner_status nedner_profile_begin(nedner_plan plan, int max_runs) {
@@ -811,6 +1271,36 @@ nedner_status nedner_profile_end(nedner_plan plan, double* ms, int max_stages, i
     for (int i = 0; i < st && i < max_stages; ++i) ms[i] = runs ? acc[i] / runs : 0.0;
   free_events(plan);
   return NEDNER_OK;
+}
+
+nedner_status nedner_get_tuning(nedner_plan plan, nedner_tuning* t) {
+  if (!plan || !t) return fail(NEDNER_E_ARG, "NULL argument");
+  get_tuning(plan->subs.empty() ? plan : plan->subs[0], t);
+  return NEDNER_OK;
+}
+
+nedner_status nedner_set_tuning(nedner_plan plan, const nedner_tuning* t) {
+  if (!plan || !t) return fail(NEDNER_E_ARG, "NULL argument");
+  if (!plan->subs.empty()) return fail(NEDNER_E_UNSUPPORTED, "set_tuning applies to single-problem plans");
+  if (plan->broken) return fail(NEDNER_E_STATE, "plan is unusable after an earlier HIP error");
+  if (!pass_shape_ok(t->pass_lines, t->pass_threads) || (t->spread_depth != 1 && t->spread_depth != 2) ||
+      t->rows_per_wave < 1)
+    return fail(NEDNER_E_ARG, "invalid tuning");
+  nedner_status st = set_spread_shape(plan, t->rows_per_wave, t->time_per_lane, t->spread_depth);
+  if (st != NEDNER_OK) return st;
+  plan->kp.pass_lines = t->pass_lines;
+  plan->kp.pass_threads = t->pass_threads;
+  plan->kp.pass_ip = t->pass_inplace != 0;
+  return NEDNER_OK;
+}
+
+nedner_status nedner_autotune(nedner_plan plan, const void* d_g, void* stream, nedner_tuning* best) {
+  if (!plan) return fail(NEDNER_E_ARG, "plan is NULL");
+  if (plan->broken) return fail(NEDNER_E_STATE, "plan is unusable after an earlier HIP error");
+  DeviceGuard guard(plan->device);
+  if (!guard.ok()) return fail(NEDNER_E_HIP, "cannot select the plan's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return plan->subs.empty() ? autotune_single(plan, d_g, s, best) : autotune_batch(plan, s, best);
 }
 
 nedner_status nedner_destroy(nedner_plan plan) {

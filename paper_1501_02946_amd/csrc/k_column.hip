@@ -14,7 +14,9 @@
 //   FFT along depth is done in LDS, so the column leaves as Z1.
 // Adjoint, per column: the exact transpose, with the interpolation turned
 // into a deterministic gather over the monotone sequence x(l).
-#include "kparams.hpp"
+#include <algorithm>
+
+#include "batch.hpp"
 
 namespace nedner {
 
@@ -155,7 +157,8 @@ __device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int wav
 // One wavefront per column; a workgroup of CPW wavefronts shares the twiddles.
 // SPEC: write the full spectrum F (N1, N2, N3) in FFT order instead of Z1.
 template <typename R, int W, bool ARGS64, bool SPEC, int PPT>
-__global__ __launch_bounds__(512) void k_column(KP p, int ncol, const cpx<R>* __restrict__ G, void* out) {
+__device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const cpx<R>* __restrict__ G,
+                                            void* out) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x, nth = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(512) void k_column(KP p, int ncol, const cpx<R>* __
   load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
   load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
   __syncthreads();
-  const int cidx = __builtin_amdgcn_readfirstlane(blockIdx.x * (nth >> 6) + wave);
+  const int cidx = __builtin_amdgcn_readfirstlane(bx * (nth >> 6) + wave);
   if (cidx >= ncol) return;
   const int k2 = cidx / p.J1, je = cidx - k2 * p.J1;
   const size_t col = cidx;
@@ -239,6 +242,11 @@ __global__ __launch_bounds__(512) void k_column(KP p, int ncol, const cpx<R>* __
   }
 }
 
+template <typename R, int W, bool ARGS64, bool SPEC, int PPT>
+__global__ __launch_bounds__(512) void k_column(KP p, int ncol, const cpx<R>* __restrict__ G, void* out) {
+  column_body<R, W, ARGS64, SPEC, PPT>(p, ncol, blockIdx.x, G, out);
+}
+
 // First index i in [lo, hi) with q[i] >= v (q non-decreasing).
 __device__ __forceinline__ int lower_bound_i(const int* q, int lo, int hi, int v) {
   while (lo < hi) {
@@ -252,8 +260,8 @@ __device__ __forceinline__ int lower_bound_i(const int* q, int lo, int hi, int v
 }
 
 template <typename R, int W, bool ARGS64, int PPT>
-__global__ __launch_bounds__(512) void k_column_adj(KP p, int ncol, int mwrap, const cpx<R>* __restrict__ Z1,
-                                                    cpx<R>* __restrict__ G) {
+__device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap, int bx,
+                                                const cpx<R>* __restrict__ Z1, cpx<R>* __restrict__ G) {
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x, nth = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -262,7 +270,7 @@ __global__ __launch_bounds__(512) void k_column_adj(KP p, int ncol, int mwrap, c
   load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
   load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
   __syncthreads();
-  const int cidx = __builtin_amdgcn_readfirstlane(blockIdx.x * (nth >> 6) + wave);
+  const int cidx = __builtin_amdgcn_readfirstlane(bx * (nth >> 6) + wave);
   if (cidx >= ncol) return;
   const int k2 = cidx / p.J1, je = cidx - k2 * p.J1;
   const size_t col = cidx;
@@ -326,6 +334,12 @@ __global__ __launch_bounds__(512) void k_column_adj(KP p, int ncol, int mwrap, c
     const int s = pmodc(n - Nt / 2, ntt);
     gc[n] = Ap[s];
   }
+}
+
+template <typename R, int W, bool ARGS64, int PPT>
+__global__ __launch_bounds__(512) void k_column_adj(KP p, int ncol, int mwrap, const cpx<R>* __restrict__ Z1,
+                                                    cpx<R>* __restrict__ G) {
+  column_adj_body<R, W, ARGS64, PPT>(p, ncol, mwrap, blockIdx.x, Z1, G);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -440,6 +454,79 @@ static hipError_t column_dispatch(const KP& p, const void* in, void* out, int sp
     case PREC_FP32P: return column_a<float, false>(p, in, out, spec, s, adj);
     default: return column_a<float, true>(p, in, out, spec, s, adj);
   }
+}
+
+// ---------------------------------------------------------------- batched
+template <typename R, int W, bool ARGS64, int PPT>
+__global__ __launch_bounds__(512) void k_column_many(const BatchProb* __restrict__ bp, WorkList wl) {
+  work_loop(wl, [&](int prob, int local) {
+    const BatchProb& B = bp[prob];
+    const KP& p = B.kp;
+    column_body<R, W, ARGS64, false, PPT>(p, p.J1 * p.K2, local, static_cast<const cpx<R>*>(B.b0), B.b1);
+  });
+}
+
+template <typename R, int W, bool ARGS64, int PPT>
+static hipError_t column_many_wp(const BatchProb* bp, const WorkList& wl, int cpw, size_t smem, hipStream_t s) {
+  if (wl.total <= 0) return hipSuccess;
+  auto k = k_column_many<R, W, ARGS64, PPT>;
+  hipError_t e = allow_smem(k, smem);
+  if (e != hipSuccess) return e;
+  int per_cu = 0, dev = 0, cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64 * cpw, smem) !=
+          hipSuccess || per_cu < 1)
+    per_cu = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int grid = (int)std::min<long>((long)per_cu * cus, wl.total);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * cpw), smem, s, bp, wl);
+  return hipGetLastError();
+}
+
+template <typename R, bool ARGS64>
+static hipError_t column_many_a(const KP& p0, int ppt, const BatchProb* bp, const WorkList& wl, int cpw,
+                                size_t smem, hipStream_t s) {
+#define NEDNER_CMP(WV)                                                                   \
+  case WV:                                                                               \
+    switch (ppt) {                                                                       \
+      case 4: return column_many_wp<R, WV, ARGS64, 4>(bp, wl, cpw, smem, s);             \
+      case 8: return column_many_wp<R, WV, ARGS64, 8>(bp, wl, cpw, smem, s);             \
+      case 16: return column_many_wp<R, WV, ARGS64, 16>(bp, wl, cpw, smem, s);           \
+      case 32: return column_many_wp<R, WV, ARGS64, 32>(bp, wl, cpw, smem, s);           \
+      default: return column_many_wp<R, WV, ARGS64, 64>(bp, wl, cpw, smem, s);           \
+    }
+  switch (p0.W) {
+    NEDNER_CMP(2)
+    NEDNER_CMP(4)
+    NEDNER_CMP(6)
+    NEDNER_CMP(8)
+    NEDNER_CMP(10)
+    NEDNER_CMP(12)
+    NEDNER_CMP(14)
+    NEDNER_CMP(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef NEDNER_CMP
+}
+
+// cpw columns per workgroup and `smem` bytes of LDS (the maxima over the batch);
+// the register bound follows the largest per-column transform in p0.
+hipError_t launch_column_many(const KP& p0, const BatchProb* bp, const WorkList& wl, int cpw, size_t smem,
+                              hipStream_t s) {
+  const int ppt = column_ppt(p0);
+  switch (p0.prec) {
+    case PREC_FP64: return column_many_a<double, true>(p0, ppt, bp, wl, cpw, smem, s);
+    case PREC_FP32P: return column_many_a<float, false>(p0, ppt, bp, wl, cpw, smem, s);
+    default: return column_many_a<float, true>(p0, ppt, bp, wl, cpw, smem, s);
+  }
+}
+
+// host helpers for the batched plan
+size_t column_wave_bytes_host(const KP& p) {
+  return p.prec == PREC_FP64 ? col_wave_bytes<double>(p.ntt, p.N3) : col_wave_bytes<float>(p.ntt, p.N3);
+}
+size_t column_shared_bytes_host(const KP& p) {
+  return p.prec == PREC_FP64 ? col_shared_bytes<double>(p.ntt, p.N3) : col_shared_bytes<float>(p.ntt, p.N3);
 }
 
 hipError_t launch_column(const KP& p, const void* G, void* out, int spectrum, hipStream_t s) {

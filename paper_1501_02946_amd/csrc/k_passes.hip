@@ -16,8 +16,9 @@
 // line for the real transforms (lat_a, pass_d, adj_d, adj_a).
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 
-#include "kparams.hpp"
+#include "batch.hpp"
 
 namespace nedner {
 
@@ -349,29 +350,6 @@ __global__ __launch_bounds__(512) void k_adj_a(KP p, int TB, const cpx<R>* __res
 
 // ---------------------------------------------------------------- launchers
 
-// Launch shape of the batched passes: lines per workgroup, threads per
-// workgroup and the transform form. The default, measured best on the C2/C3
-// workloads, is the in-place form with 16 lines (whole 128-byte rows of float
-// pairs) and 512 threads; NEDNER_PASS_SHAPE ("lines,threads,inplace")
-// overrides it for tuning.
-struct PassShape {
-  int tb, threads, ip;
-};
-
-static PassShape pass_shape(int n, size_t cs) {
-  PassShape s{16, 512, 1};
-  if (const char* e = getenv("NEDNER_PASS_SHAPE")) {
-    int a = 0, b = 0, c = 0;
-    if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a > 0 && (a & (a - 1)) == 0 && b >= 64 && b <= 512 &&
-        b % 64 == 0)
-      s = PassShape{a, b, c != 0};
-  }
-  // keep within the LDS of a CU and, in place, within 8 points per thread
-  while (s.tb > 1 && (size_t)n * cs * ((s.ip ? 1 : 2) * (size_t)s.tb + 1) > 160 * 1024) s.tb >>= 1;
-  while (s.ip && s.tb > 1 && (size_t)n * s.tb > 8 * (size_t)s.threads) s.tb >>= 1;
-  return s;
-}
-
 template <typename R>
 static size_t smem_for(int n, int TB, bool ip) {
   return (size_t)n * sizeof(cpx<R>) * ((ip ? 1 : 2) * (size_t)TB + 1);
@@ -381,17 +359,17 @@ static size_t smem_for(int n, int TB, bool ip) {
   template <typename R>                                                                         \
   static hipError_t run_##KERNEL(const KP& p, const void* in, void* out, hipStream_t s) {        \
     const int n = (NLEN);                                                                       \
-    const PassShape ps = pass_shape(n, sizeof(cpx<R>));                                         \
-    const int TB = ps.tb;                                                                       \
-    const size_t sh = smem_for<R>(n, TB, ps.ip);                                                \
+    const int TB = pass_lines_for(p, n, (int)sizeof(cpx<R>));                                   \
+    const bool ip = p.pass_ip != 0;                                                             \
+    const size_t sh = smem_for<R>(n, TB, ip);                                                   \
     dim3 grid(((GYLINES) + TB - 1) / TB, (GX));                                                 \
-    hipError_t e = ps.ip ? allow_smem(KERNEL<R, true>, sh) : allow_smem(KERNEL<R, false>, sh);  \
+    hipError_t e = ip ? allow_smem(KERNEL<R, true>, sh) : allow_smem(KERNEL<R, false>, sh);     \
     if (e != hipSuccess) return e;                                                              \
-    if (ps.ip)                                                                                  \
-      hipLaunchKernelGGL((KERNEL<R, true>), grid, dim3(ps.threads), sh, s, p, TB,               \
+    if (ip)                                                                                     \
+      hipLaunchKernelGGL((KERNEL<R, true>), grid, dim3(p.pass_threads), sh, s, p, TB,           \
                          static_cast<const IN_T*>(in), static_cast<OUT_T*>(out));               \
     else                                                                                        \
-      hipLaunchKernelGGL((KERNEL<R, false>), grid, dim3(ps.threads), sh, s, p, TB,              \
+      hipLaunchKernelGGL((KERNEL<R, false>), grid, dim3(p.pass_threads), sh, s, p, TB,          \
                          static_cast<const IN_T*>(in), static_cast<OUT_T*>(out));               \
     return hipGetLastError();                                                                   \
   }
@@ -404,6 +382,62 @@ NEDNER_PASS_LAUNCH(k_adj_d, p.N2, p.N1, p.N3 / 2, R, cpx<R>)
 NEDNER_PASS_LAUNCH(k_adj_c, p.N1, p.K2, p.N3, cpx<R>, cpx<R>)
 NEDNER_PASS_LAUNCH(k_adj_b, p.n1, p.K2, p.Nt, cpx<R>, cpx<R>)
 NEDNER_PASS_LAUNCH(k_adj_a, p.n2, p.n1, p.Nt / 2, cpx<R>, R)
+
+// ---------------------------------------------------------------- batched
+// One persistent kernel for the four forward passes; the stage picks the pass.
+// Per problem: transform length n, number of lines, grid height, in and out.
+template <typename R, bool IP>
+__global__ __launch_bounds__(512) void k_pass_many(const BatchProb* __restrict__ bp, WorkList wl, int stage) {
+  work_loop(wl, [&](int prob, int local) {
+    const BatchProb& B = bp[prob];
+    const KP& p = B.kp;
+    const int cs = (int)sizeof(cpx<R>);
+    if (stage == ST_LAT_A) {
+      const int TB = pass_lines_for(p, p.n2, cs), gx = (p.Nt / 2 + TB - 1) / TB;
+      lat_a_body<R, IP>(p, TB, local % gx, local / gx, static_cast<const R*>(B.b0),
+                        static_cast<cpx<R>*>(B.b1));
+    } else if (stage == ST_LAT_B) {
+      const int TB = pass_lines_for(p, p.n1, cs), gx = (p.Nt + TB - 1) / TB;
+      lat_b_body<R, IP>(p, TB, local % gx, local / gx, static_cast<const cpx<R>*>(B.b1),
+                        static_cast<cpx<R>*>(B.b0));
+    } else if (stage == ST_PASS_C) {
+      const int TB = pass_lines_for(p, p.N1, cs), gx = (p.N3 + TB - 1) / TB;
+      pass_c_body<R, IP>(p, TB, local % gx, local / gx, static_cast<const cpx<R>*>(B.b1),
+                         static_cast<cpx<R>*>(B.b0));
+    } else {
+      const int TB = pass_lines_for(p, p.N2, cs), gx = (p.N3 / 2 + TB - 1) / TB;
+      pass_d_body<R, IP>(p, TB, local % gx, local / gx, static_cast<const cpx<R>*>(B.b0),
+                         static_cast<R*>(B.out));
+    }
+  });
+}
+
+template <typename R, bool IP>
+static hipError_t pass_many_r(const KP& p0, int stage, const BatchProb* bp, const WorkList& wl, size_t smem,
+                              hipStream_t s) {
+  if (wl.total <= 0) return hipSuccess;
+  auto k = k_pass_many<R, IP>;
+  hipError_t e = allow_smem(k, smem);
+  if (e != hipSuccess) return e;
+  int per_cu = 0, dev = 0, cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), p0.pass_threads,
+                                                  smem) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int grid = (int)std::min<long>((long)per_cu * cus, wl.total);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(p0.pass_threads), smem, s, bp, wl, stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_many(const KP& p0, int stage, const BatchProb* bp, const WorkList& wl, size_t smem,
+                            hipStream_t s) {
+  if (p0.prec == PREC_FP64)
+    return p0.pass_ip ? pass_many_r<double, true>(p0, stage, bp, wl, smem, s)
+                      : pass_many_r<double, false>(p0, stage, bp, wl, smem, s);
+  return p0.pass_ip ? pass_many_r<float, true>(p0, stage, bp, wl, smem, s)
+                    : pass_many_r<float, false>(p0, stage, bp, wl, smem, s);
+}
 
 #define NEDNER_PASS_ENTRY(NAME, KERNEL)                                                   \
   hipError_t NAME(const KP& p, const void* in, void* out, hipStream_t s) {                \

@@ -14,7 +14,7 @@
 // plan time, each entry carrying the sensor index and its weight for this
 // column. There are no atomics: every output element is written once, by one
 // lane, in a fixed order, so the result is bitwise deterministic.
-#include "kparams.hpp"
+#include "batch.hpp"
 
 namespace nedner {
 
@@ -353,6 +353,103 @@ static hipError_t dispatch(const KP& p, const void* a, void* b, hipStream_t s, b
       return p.wide_w ? spread_p<float, double, double>(p, a, b, vec_ok(p, a, b, 4), s, adj)
                       : spread_p<float, float, double>(p, a, b, vec_ok(p, a, b, 4), s, adj);
     default: return spread_p<float, float, float>(p, a, b, vec_ok(p, a, b, 4), s, adj);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched: one persistent launch over all problems
+
+template <int W, int TT, typename R, typename WT, typename A, bool VEC, int PD>
+__global__ __launch_bounds__(256) void k_spread_many(const BatchProb* __restrict__ bp, WorkList wl) {
+  work_loop(wl, [&](int prob, int local) {
+    const BatchProb& B = bp[prob];
+    const KP& p = B.kp;
+    spread_body<W, TT, R, WT, A, VEC, PD>(p, local, p.cellbeg, p.ent_m,
+                                          static_cast<const WT*>(p.ent_w2),
+                                          static_cast<const WT*>(p.w1), static_cast<const R*>(B.g),
+                                          static_cast<R*>(B.b0));
+  });
+}
+
+__global__ void k_batch_prepare(BatchProb* bp, PtrChunk c, int* counters, int ncounters) {
+  const int i = threadIdx.x;
+  if (i < c.n) {
+    bp[c.first + i].g = c.g[i];
+    bp[c.first + i].out = c.out[i];
+  }
+  if (i < ncounters) counters[i] = 0;
+}
+
+hipError_t launch_batch_prepare(BatchProb* bp, const PtrChunk& c, int* counters, int ncounters,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_prepare, dim3(1), dim3(64), 0, s, bp, c, counters, ncounters);
+  return hipGetLastError();
+}
+
+// resident workgroups of a persistent launch: every CU filled to occupancy
+template <typename K>
+static int persistent_grid(K kernel, int threads, size_t smem, int total) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), threads,
+                                                  smem) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  const long g = (long)per_cu * cus;
+  return (int)(g < total ? g : total);
+}
+
+template <typename R, typename WT, typename A, int W, int TT>
+static hipError_t spread_many_wt(const BatchProb* bp, const WorkList& wl, bool vec, bool deep,
+                                 hipStream_t s) {
+  if (wl.total <= 0) return hipSuccess;
+#define NEDNER_SM(V, D)                                                                         \
+  {                                                                                              \
+    auto k = k_spread_many<W, TT, R, WT, A, V, D>;                                               \
+    hipLaunchKernelGGL(k, dim3(persistent_grid(k, 256, 0, wl.total)), dim3(256), 0, s, bp, wl);  \
+    return hipGetLastError();                                                                    \
+  }
+  if (vec && deep) NEDNER_SM(true, 2)
+  if (vec) NEDNER_SM(true, 1)
+  NEDNER_SM(false, 1)
+#undef NEDNER_SM
+}
+
+template <typename R, typename WT, typename A>
+static hipError_t spread_many_p(const KP& p0, const BatchProb* bp, const WorkList& wl, bool vec,
+                                hipStream_t s) {
+  const bool deep = p0.spread_pd == 2;
+#define NEDNER_SMW(WV)                                                            \
+  case WV:                                                                        \
+    switch (p0.TT) {                                                              \
+      case 1: return spread_many_wt<R, WT, A, WV, 1>(bp, wl, vec, deep, s);       \
+      case 2: return spread_many_wt<R, WT, A, WV, 2>(bp, wl, vec, deep, s);       \
+      case 4: return spread_many_wt<R, WT, A, WV, 4>(bp, wl, vec, deep, s);       \
+      default: return hipErrorInvalidValue;                                       \
+    }
+  switch (p0.W) {
+    NEDNER_SMW(2)
+    NEDNER_SMW(4)
+    NEDNER_SMW(6)
+    NEDNER_SMW(8)
+    NEDNER_SMW(10)
+    NEDNER_SMW(12)
+    NEDNER_SMW(14)
+    NEDNER_SMW(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef NEDNER_SMW
+}
+
+hipError_t launch_spread_many(const KP& p0, const BatchProb* bp, const WorkList& wl, int vec,
+                              hipStream_t s) {
+  switch (p0.prec) {
+    case PREC_FP64: return spread_many_p<double, double, double>(p0, bp, wl, vec != 0, s);
+    case PREC_FP32C:
+      return p0.wide_w ? spread_many_p<float, double, double>(p0, bp, wl, vec != 0, s)
+                       : spread_many_p<float, float, double>(p0, bp, wl, vec != 0, s);
+    default: return spread_many_p<float, float, float>(p0, bp, wl, vec != 0, s);
   }
 }
 

@@ -31,6 +31,9 @@ struct KP {
   int prec;       // Prec
   int spread_pd;  // software pipeline depth of the spreading sweep (1 or 2)
   int wide_w;     // FP32C: 8-byte first-axis weights (fetched at use) instead of 4-byte
+  int pass_lines; // FFT passes: lines per workgroup (power of two, upper bound)
+  int pass_threads; // FFT passes: threads per workgroup (multiple of 64, <= 512)
+  int pass_ip;    // FFT passes: in-place (1) or ping-pong (0) transform
 
   // ---- window and frequency constants (double, reduced on the host) -----
   double beta;      // phi(x) = exp(-beta x^2), x in grid units, all three axes
@@ -70,6 +73,16 @@ struct Bufs {
   void* Z1;  // after depth IFFT   [K2][J1][N3] complex
   void* Z2;  // after first-axis IFFT [K2][N1][N3] complex
 };
+
+// Lines per workgroup of a batched FFT pass over lines of length n: the
+// plan's upper bound, reduced to fit 160 KB of LDS and, in place, 8 points
+// per thread. Shared by the single and the batched launches.
+__host__ __device__ inline int pass_lines_for(const KP& p, int n, int cs) {
+  int tb = p.pass_lines;
+  while (tb > 1 && (long)n * cs * ((p.pass_ip ? 1 : 2) * (long)tb + 1) > 160 * 1024) tb >>= 1;
+  while (p.pass_ip && tb > 1 && (long)n * tb > 8L * p.pass_threads) tb >>= 1;
+  return tb;
+}
 
 // Allow a kernel more than 64 KB of dynamic LDS (gfx950 has 160 KB per CU).
 template <typename F>

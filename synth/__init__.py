@@ -19,7 +19,8 @@ Workload recipes (all with sound speed c = 1 and aperture [0,1)^2):
   output 192x192x384.
 * ``c4``: 64 problems, M uniform in [1024, 16384] kept from a ceil(sqrt(M))^2
   jittered grid, Nt in {256, 512, 1024}, 1-10 balls each, output s x s x Nt/2
-  with s the smallest 5-smooth integer >= ceil(sqrt(M)).
+  with s the smallest even 5-smooth integer >= ceil(sqrt(M)) (the mode sets
+  {-N/2..N/2-1} need even N).
 
 Time span T = Nt*dt = 1 everywhere (dt = 1/Nt), depth step d3 = c*T/N3.
 """
@@ -77,15 +78,15 @@ class Problem:
                     a2=self.a2, d1=self.d1, d2=self.d2, d3=self.d3)
 
 
-def five_smooth_at_least(n: int) -> int:
-    """Smallest integer >= n whose prime factors are all in {2, 3, 5}."""
+def five_smooth_at_least(n: int, even: bool = False) -> int:
+    """Smallest integer >= n whose prime factors are all in {2, 3, 5} (even if asked)."""
     k = max(1, int(n))
     while True:
         r = k
         for p in (2, 3, 5):
             while r % p == 0:
                 r //= p
-        if r == 1:
+        if r == 1 and (not even or k % 2 == 0):
             return k
         k += 1
 
@@ -254,7 +255,7 @@ def batch_c4(seed: int = 0, count: int = 64):
         keep = np.sort(rng.choice(s * s, size=m, replace=False))
         xy = grid[keep]
         nt = int(rng.choice([256, 512, 1024]))
-        n = five_smooth_at_least(s)
+        n = five_smooth_at_least(s, even=True)
         balls = random_balls(int(rng.integers(1, 11)), rng)
         probs.append(make_problem(xy, np.full(m, 1.0 / m), balls, nt, n, n, nt // 2,
                                   name="c4"))

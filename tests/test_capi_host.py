@@ -195,3 +195,22 @@ def test_binding_struct_layout_matches_header():
             if part:
                 fields.append(part)
     assert fields == [f for f, _ in N.desc_struct._fields_]
+
+
+def test_batch_descriptor_checks_before_any_device_work():
+    L = N.lib()
+    d0, k0 = _desc()
+    d1, k1 = _desc(precision="fp64")
+    arr = (N.desc_struct * 2)(d0, d1)
+    plan = ctypes.c_void_p()
+    assert L.nedner_plan_create_many(arr, 2, 0, None, ctypes.byref(plan)) == E_ARG
+    assert b"precision" in L.nedner_last_error()
+    d2, k2 = _desc(w=8)
+    arr = (N.desc_struct * 2)(d0, d2)
+    assert L.nedner_plan_create_many(arr, 2, 0, None, ctypes.byref(plan)) == E_ARG
+    assert L.nedner_plan_create_many(arr, 0, 0, None, ctypes.byref(plan)) == E_ARG
+    assert L.nedner_execute_many(None, None, None, 0, None) == E_ARG
+    t = N.tuning_struct()
+    assert L.nedner_get_tuning(None, ctypes.byref(t)) == E_ARG
+    assert L.nedner_set_tuning(None, ctypes.byref(t)) == E_ARG
+    assert L.nedner_autotune(None, None, None, ctypes.byref(t)) == E_ARG
