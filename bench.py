@@ -65,25 +65,79 @@ def stage_model(p, info, prec):
     }
 
 
-def kernel_source_hash():
+# kernel name prefix -> stage, and the source file that defines the kernel
+STAGE_KERNELS = {
+    "k_spread": ("spread", "k_spread.hip"), "k_lat_a": ("lat_a", "k_passes.hip"),
+    "k_lat_b": ("lat_b", "k_passes.hip"), "k_column": ("column", "k_column_impl.hpp"),
+    "k_pass_c": ("pass_c", "k_passes.hip"), "k_pass_d": ("pass_d", "k_passes.hip"),
+}
+
+
+def kernel_source_hash(stage):
+    """Hash of the source that defines a stage's kernel and the shared transform code."""
+    src = {v[0]: v[1] for v in STAGE_KERNELS.values()}[stage]
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1501_02946_amd", "csrc"))):
+    for f in (src, "fft_lds.hpp"):
         with open(os.path.join(ROOT, "paper_1501_02946_amd", "csrc", f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, prec, stage):
-    """HBM bytes per launch from committed rocprofv3 counters, if still current."""
+def measured_traffic(workload, prec, stage, tuning):
+    """HBM bytes per launch from committed rocprofv3 counters, if still current:
+    same kernel source and same launch shape, else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
     rec = d.get(f"{workload}:{prec}:{stage}")
-    if not rec or rec.get("source_hash") != kernel_source_hash():
+    if not rec or rec.get("source_hash") != kernel_source_hash(stage):
+        return None
+    if rec.get("tuning") != {k: tuning[k] for k in rec.get("tuning", {})}:
         return None
     return rec.get("bytes")
+
+
+def _counter_means(path):
+    """Mean counter value per kernel (KiB per dispatch) of a rocprofv3 counter CSV."""
+    import csv
+    acc = {}
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").strip()
+            name = name.split("::")[-1]
+            acc.setdefault(name, []).append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def summarize_counters(root, workload, prec, tuning):
+    """HBM traffic per stage from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)
+    of this script, each scaled by what the same counter reads for a plain
+    device copy of known size (the --copy-calibration run)."""
+    out, lines = {}, []
+    scale = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        cal = _counter_means(os.path.join(root, f"pmc_{c}", "copy_counter_collection.csv"))
+        kib, _ = cal["__amd_rocclr_copyBuffer"]
+        # the copy reads and writes copy_bytes each
+        with open(os.path.join(root, "copy_calibration.json")) as fh:
+            nbytes = json.load(fh)["copy_bytes"]
+        scale[c] = nbytes / (kib * 1024.0)
+    fetch = _counter_means(os.path.join(root, "pmc_FETCH_SIZE", f"{workload}_counter_collection.csv"))
+    write = _counter_means(os.path.join(root, "pmc_WRITE_SIZE", f"{workload}_counter_collection.csv"))
+    for kname, (stage, _) in STAGE_KERNELS.items():
+        hit = [k for k in fetch if k == kname]
+        if not hit or kname not in write:
+            continue
+        fk, n = fetch[kname]
+        wk, _ = write[kname]
+        b = fk * 1024 * scale["FETCH_SIZE"] + wk * 1024 * scale["WRITE_SIZE"]
+        out[f"{workload}:{prec}:{stage}"] = dict(
+            bytes=int(round(b)), fetch_kib=round(fk, 1), write_kib=round(wk, 1),
+            fetch_scale=round(scale["FETCH_SIZE"], 4), write_scale=round(scale["WRITE_SIZE"], 4),
+            dispatches=n, source_hash=kernel_source_hash(stage), tuning=tuning)
+    return out
 
 
 def time_steps(torch, plan, g, out, steps, warmup, profile=False):
@@ -172,6 +226,41 @@ def bench_batch(a, torch, N, synth):
             "autotune": tune, "roofline": None, "cpu_baseline": None}
 
 
+def write_traffic(a):
+    """Merge the measured per-stage HBM bytes into profiles/traffic.json and print
+    them next to the algorithmic bytes, with the launch shape of the counted run."""
+    import paper_1501_02946_amd as N
+    import synth
+    import torch  # noqa: F401  (the binding loads torch first)
+    p = synth.config(a.workload)
+    info = N.query(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), h=p.h, c=p.c, t0=p.t0,
+                   precision=a.precision)
+    # the JSON line the FETCH_SIZE-counted bench run printed: its launch shape
+    with open(os.path.join(a.summarize_counters, "bench_line.json")) as fh:
+        tuning = json.loads(fh.read().strip().splitlines()[-1])["tuning"]
+    rec = summarize_counters(a.summarize_counters, a.workload, a.precision, tuning)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    d = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            d = json.load(fh)
+    d.update(rec)
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    model = stage_model(p, info, a.precision)
+    print("| stage | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | algorithmic bytes | ratio |")
+    print("|---|---|---|---|---|---|")
+    for k, r in rec.items():
+        st = k.split(":")[-1]
+        alg = model[st]["bytes"]
+        print(f"| {st} | {r['fetch_kib']} | {r['write_kib']} | {r['bytes']} | {alg} | "
+              f"{r['bytes'] / alg:.3f} |")
+    print(f"scale factors: FETCH_SIZE x{next(iter(rec.values()))['fetch_scale']}, "
+          f"WRITE_SIZE x{next(iter(rec.values()))['write_scale']}")
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,7 +272,11 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
+    ap.add_argument("--summarize-counters", metavar="DIR", default=None,
+                    help="turn the rocprofv3 counter CSVs under DIR into profiles/traffic.json")
     a = ap.parse_args(argv)
+    if a.summarize_counters:
+        return write_traffic(a)
     if a.copy_calibration:
         import torch
         x = torch.ones(a.copy_calibration * (1 << 18), dtype=torch.float32, device="cuda")
@@ -241,7 +334,8 @@ def main(argv=None):
                     frac=round(ach / HBM_PEAK_GBS, 4))
     roof["kernel"] = dom
     roof["ms"] = round(stages[dom], 5)
-    roof["traffic"] = measured_traffic(a.workload, a.precision, dom)
+    tuning = {k: v for k, v in plan.tuning.items() if not k.startswith("ms_")}
+    roof["traffic"] = measured_traffic(a.workload, a.precision, dom, tuning)
 
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1,
@@ -252,6 +346,7 @@ def main(argv=None):
                    "nt": p.nt, "volume": [p.n1, p.n2, p.n3], "precision": a.precision,
                    "window_taps": 12, "oversampling": 2},
         "volumes_per_s": round(1e3 / ms, 2),
+        "tuning": tuning,
         "roofline": roof,
         "stages": stage_rep,
     }

@@ -129,7 +129,8 @@ typedef struct {
 typedef struct {
   int32_t rows_per_wave;   /* spreading sweep length (rows of the oversampled grid) */
   int32_t time_per_lane;   /* spreading time samples per lane: 1, 2 or 4 */
-  int32_t spread_depth;    /* spreading software pipeline depth: 1 or 2 */
+  int32_t spread_depth;    /* spreading sweep: 1 = samples staged through LDS in batches,
+                              2 = two-deep register pipeline */
   int32_t pass_lines;      /* FFT passes: lines per workgroup (power of two) */
   int32_t pass_threads;    /* FFT passes: threads per workgroup (64..512, multiple of 64) */
   int32_t pass_inplace;    /* FFT passes: in-place (1) or ping-pong (0) transform */

@@ -86,9 +86,10 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t real_size(int prec) { return prec == NEDNER_FP64 ? 8 : 4; }
 // Tuning overrides read at plan creation: NEDNER_SPREAD="depth,wide" sets the
-// spreading pipeline depth (1 or 2) and, for FP32C, 8-byte weights (0 or 1).
+// spreading sweep (1: samples staged through LDS, 2: two-deep register
+// pipeline) and, for FP32C, 8-byte weights (0 or 1).
 struct SpreadOpt {
-  int pd = 2, wide = 1;
+  int pd = 1, wide = 1;
 };
 SpreadOpt spread_opt() {
   SpreadOpt o;
@@ -123,7 +124,7 @@ void workspace_layout(const nedner_desc& d, const Derived& v, size_t* off1, size
 // LDS of a column workgroup with one column: shared twiddles + one wave's buffers.
 size_t column_lds(const nedner_desc& d, const Derived& v) {
   const size_t rs = real_size(d.prec), cs = 2 * rs;
-  const size_t nbuf = std::max<size_t>(v.ntt, d.n3);
+  const size_t nbuf = std::max<size_t>(v.ntt, d.n3) + nedner::COL_EXT;
   const size_t wave = (cs * (nbuf + d.n3 + 1) + (rs + 4) * (d.n3 + 1) + 15) & ~size_t(15);
   return cs * (v.ntt + d.n3) + wave;
 }
@@ -360,6 +361,28 @@ struct DevAlloc {
   }
 };
 
+// Device spreading lists of one geometry. The sensor indices and weights are
+// padded with zeros past the end so that the staged sweep may read ahead.
+struct ListTables {
+  const int* em = nullptr;
+  const void* ew = nullptr;
+  const int* cb = nullptr;
+};
+constexpr int LIST_PAD = 16;
+
+ListTables upload_lists(const Geometry& G, bool wide, DevAlloc& L) {
+  ListTables t;
+  const size_t n = G.ent_m.size();
+  std::vector<int> em(G.ent_m);
+  em.resize(n + LIST_PAD, 0);
+  std::vector<double> ew(G.ent_w2);
+  ew.resize(n + LIST_PAD, 0.0);
+  t.em = static_cast<const int*>(L.upload(em));
+  t.ew = wide ? L.upload(ew) : L.upload_as<float>(ew);
+  t.cb = static_cast<const int*>(L.upload(G.cellbeg));
+  return t;
+}
+
 }  // namespace
 
 struct nedner_plan_s {
@@ -543,9 +566,10 @@ nedner_status create_one(const nedner_desc* desc, int device, nedner_plan* out) 
   k.cell = static_cast<const int*>(A.upload(G.cell));
   {
     DevAlloc Lst;
-    k.ent_w2 = wide ? Lst.upload(G.ent_w2) : Lst.upload_as<float>(G.ent_w2);
-    k.ent_m = static_cast<const int*>(Lst.upload(G.ent_m));
-    k.cellbeg = static_cast<const int*>(Lst.upload(G.cellbeg));
+    const ListTables t = upload_lists(G, wide, Lst);
+    k.ent_m = t.em;
+    k.ent_w2 = t.ew;
+    k.cellbeg = t.cb;
     p->list_allocs = Lst.ptrs;
     if (Lst.err != hipSuccess && A.err == hipSuccess) A.err = Lst.err;
   }
@@ -890,9 +914,7 @@ nedner_status set_spread_shape(nedner_plan p, int S, int TT, int PD) {
   DeviceGuard guard(p->device);
   DevAlloc L;
   const bool wide = p->kp.prec == NEDNER_FP64 || p->kp.wide_w;
-  const void* ew = wide ? L.upload(G.ent_w2) : L.upload_as<float>(G.ent_w2);
-  const void* em = L.upload(G.ent_m);
-  const void* cb = L.upload(G.cellbeg);
+  const ListTables t = upload_lists(G, wide, L);
   if (L.err != hipSuccess) {
     for (void* q : L.ptrs) (void)hipFree(q);
     return fail(L.err == hipErrorOutOfMemory ? NEDNER_E_OOM : NEDNER_E_HIP,
@@ -901,9 +923,9 @@ nedner_status set_spread_shape(nedner_plan p, int S, int TT, int PD) {
   for (void* q : p->list_allocs) (void)hipFree(q);
   p->list_allocs = L.ptrs;
   KP& k = p->kp;
-  k.ent_w2 = ew;
-  k.ent_m = static_cast<const int*>(em);
-  k.cellbeg = static_cast<const int*>(cb);
+  k.ent_m = t.em;
+  k.ent_w2 = t.ew;
+  k.cellbeg = t.cb;
   k.TT = v.TT;
   k.S = v.S;
   k.nseg = v.nseg;
@@ -1036,7 +1058,8 @@ nedner_status autotune_single(nedner_plan p, const void* d_g, hipStream_t s, ned
   void* vol = nullptr;
   const size_t vb = (size_t)p->kp.N1 * p->kp.N2 * p->kp.N3 * (p->kp.prec == NEDNER_FP64 ? 8 : 4);
   if (hipMalloc(&vol, vb) != hipSuccess) return fail(NEDNER_E_OOM, "autotune: no memory for a volume");
-  const int cand[][3] = {{16, 512, 1}, {8, 512, 1}, {16, 256, 1}, {8, 256, 1}, {16, 256, 0}, {8, 256, 0}, {16, 512, 0}};
+  const int cand[][3] = {{16, 512, 1}, {32, 512, 1}, {8, 512, 1}, {16, 256, 1}, {32, 256, 1},
+                         {8, 256, 1},  {16, 256, 0}, {8, 256, 0}, {16, 512, 0}};
   KP& k = p->kp;
   int bl = k.pass_lines, bt = k.pass_threads, bi = k.pass_ip;
   double best = 1e300;

@@ -252,6 +252,27 @@ __device__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, in
   }
 }
 
+// Fill dst[0, total) with f(i) (each f typically one global load), thread tid
+// of nth taking i = tid, tid + nth, ... . Up to BATCH loads per thread are in
+// flight before the first LDS store, so their latencies overlap instead of
+// adding up as they do when every store waits for its own load.
+template <int BATCH, typename T, typename F>
+__device__ __forceinline__ void stage_in(cpx<T>* dst, int total, int tid, int nth, F&& f) {
+  for (int base = 0; base < total; base += BATCH * nth) {
+    cpx<T> v[BATCH];
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int i = base + tid + q * nth;
+      v[q] = i < total ? f(i) : cpx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int i = base + tid + q * nth;
+      if (i < total) dst[i] = v[q];
+    }
+  }
+}
+
 // Stage a twiddle table of n entries from global memory into LDS.
 template <typename T>
 __device__ __forceinline__ void load_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ src, int n,

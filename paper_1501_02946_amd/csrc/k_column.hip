@@ -1,452 +1,18 @@
-// NER step (eq. (6)-(8)) fused with the inversion weight of eq. (1), one
-// workgroup per column (j1, k2) of the NED result.
-//
-// Forward, per column:
-//   a[n'] = G(n' + Nt/2), n' in [-Nt/2, Nt/2), stored at n' mod ntt, zero padded
-//           (G already carries 1/phihat_t, applied in the lateral pass);
-//   B = FFT_ntt(a) in LDS;
-//   for l in -N3/2..N3/2 (both depth Nyquist representatives):
-//     x = omega dt ntt/(2 pi) = sign(l) c dt ntt |K|/(2 pi), reduced in double;
-//     H = sum over the W grid points q nearest x of B[q mod ntt] phi(x - q);
-//     F = scale * W(j,l) * H * exp(-i (Nt/2 theta + omega t0)), phase in double;
-//   then either the spectrum is written out, or the Nyquist combination of
-//   the half-spectrum inverse (see column_policy) is applied and the inverse
-//   FFT along depth is done in LDS, so the column leaves as Z1.
-// Adjoint, per column: the exact transpose, with the interpolation turned
-// into a deterministic gather over the monotone sequence x(l).
-#include <algorithm>
-
-#include "batch.hpp"
+// Host-side dispatch of the NER column kernels (k_column_impl.hpp) over the
+// precisions, each of which is compiled in a translation unit of its own.
+#include "k_column_impl.hpp"
 
 namespace nedner {
 
-__device__ __forceinline__ int pmodc(int a, int n) {
-  int r = a % n;
-  return r < 0 ? r + n : r;
-}
-
-// How column (je, k2) enters the half-spectrum inverse transform.
-//   fac: overall factor; pol: depth Nyquist slot gets F(-N3/2) (0), F(+N3/2) (1)
-//   or their mean (2). The real part of the full inverse DFT equals a C2R along
-//   the second axis of the symmetrised half spectrum; at the Nyquist indices the
-//   symmetrisation averages the two representatives -N/2 and +N/2.
-__device__ __forceinline__ void column_policy(int je, int k2, int N1, int N2, double& fac, int& pol) {
-  const bool lo = je == 0, hi = je == N1;
-  if (k2 == 0) {
-    fac = hi ? 0.0 : 1.0;
-    pol = 0;
-  } else if (k2 == N2 / 2) {
-    fac = lo ? 0.0 : 1.0;
-    pol = 1;
-  } else if (lo) {
-    fac = 0.5;
-    pol = 0;
-  } else if (hi) {
-    fac = 0.5;
-    pol = 1;
-  } else {
-    fac = 1.0;
-    pol = 2;
-  }
-}
-
-template <typename R>
-__device__ __forceinline__ R wexp(R v);
-template <>
-__device__ __forceinline__ float wexp<float>(float v) { return __expf(v); }
-template <>
-__device__ __forceinline__ double wexp<double>(double v) { return exp(v); }
-
-template <typename R>
-__device__ __forceinline__ void sincos_pi(R v, R* s, R* c);
-template <>
-__device__ __forceinline__ void sincos_pi<float>(float v, float* s, float* c) { sincospif(v, s, c); }
-template <>
-__device__ __forceinline__ void sincos_pi<double>(double v, double* s, double* c) { sincospi(v, s, c); }
-
-// Frequency data of one output l of a column: grid position x = q0 + fr,
-// the weight W(j,l) times the scale, and exp(-i phase).
-template <typename R, bool ARGS64>
-struct LPoint {
-  int q0;
-  R fr;
-  R wgt;
-  cpx<R> ph;
-};
-
-template <typename R, bool ARGS64>
-__device__ __forceinline__ LPoint<R, ARGS64> lpoint(const KP& p, double a, int l, double scale) {
-  LPoint<R, ARGS64> o;
-  const double l2 = double(l) * double(l);
-  R rr;
-  if constexpr (ARGS64) {
-    const double kk = sqrt(a + l2 * p.bz);
-    const double x = (l > 0 ? 1.0 : (l < 0 ? -1.0 : 0.0)) * p.cdtnt * kk;
-    const double fl = floor(x);
-    o.q0 = int(fl);
-    o.fr = R(x - fl);
-    double r = x * p.phase_p;
-    r -= rint(r);
-    rr = R(r);
-    double w = 0.0;
-    if (l != 0)
-      w = p.two_c * fabs(double(l)) * sqrt(p.bz) / kk;
-    else if (a == 0.0)
-      w = p.two_c;
-    o.wgt = R(w * scale);
-  } else {
-    const float kk = sqrtf(float(a) + float(l2) * float(p.bz));
-    const float x = (l > 0 ? 1.0f : (l < 0 ? -1.0f : 0.0f)) * float(p.cdtnt) * kk;
-    const float fl = floorf(x);
-    o.q0 = int(fl);
-    o.fr = R(x - fl);
-    float r = x * float(p.phase_p);
-    r -= rintf(r);
-    rr = R(r);
-    float w = 0.0f;
-    if (l != 0)
-      w = float(p.two_c) * fabsf(float(l)) * sqrtf(float(p.bz)) / kk;
-    else if (a == 0.0)
-      w = float(p.two_c);
-    o.wgt = R(w * float(scale));
-  }
-  R s, c;
-  sincos_pi<R>(R(2) * rr, &s, &c);
-  o.ph = cpx<R>{c, -s};
-  return o;
-}
-
-// LDS of one workgroup: the two twiddle tables, shared, then per wavefront
-// (one column each) two transform buffers and the per-l arrays.
-template <typename R>
-struct ColSmem {
-  cpx<R>* twt;  // ntt twiddles
-  cpx<R>* tw3;  // N3 twiddles
-  cpx<R>* a;    // nbuf: the transform buffer (in place)
-  cpx<R>* fl;   // N3 + 1
-  R* fr;        // N3 + 1 (adjoint)
-  int* q0;      // N3 + 1 (adjoint)
-};
-
-template <typename R>
-__host__ __device__ inline size_t col_wave_bytes(int ntt, int N3) {
-  const size_t nbuf = ntt > N3 ? ntt : N3;
-  size_t b = sizeof(cpx<R>) * (nbuf + N3 + 1) + (sizeof(R) + sizeof(int)) * ((size_t)N3 + 1);
-  return (b + 15) & ~size_t(15);
-}
-
-template <typename R>
-__host__ __device__ inline size_t col_shared_bytes(int ntt, int N3) {
-  return sizeof(cpx<R>) * ((size_t)ntt + N3);
-}
-
-template <typename R>
-__device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int wave) {
-  ColSmem<R> s;
-  const int nbuf = p.ntt > p.N3 ? p.ntt : p.N3;
-  s.twt = reinterpret_cast<cpx<R>*>(smem);
-  s.tw3 = s.twt + p.ntt;
-  char* w = smem + col_shared_bytes<R>(p.ntt, p.N3) + (size_t)wave * col_wave_bytes<R>(p.ntt, p.N3);
-  s.a = reinterpret_cast<cpx<R>*>(w);
-  s.fl = s.a + nbuf;
-  s.fr = reinterpret_cast<R*>(s.fl + p.N3 + 1);
-  s.q0 = reinterpret_cast<int*>(s.fr + p.N3 + 1);
-  return s;
-}
-
-// One wavefront per column; a workgroup of CPW wavefronts shares the twiddles.
-// SPEC: write the full spectrum F (N1, N2, N3) in FFT order instead of Z1.
-template <typename R, int W, bool ARGS64, bool SPEC, int PPT>
-__device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const cpx<R>* __restrict__ G,
-                                            void* out) {
-  extern __shared__ __align__(16) char smem[];
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int ntt = p.ntt, N3 = p.N3, Nt = p.Nt, h3 = N3 / 2;
-  ColSmem<R> sm = col_carve<R>(smem, p, wave);
-  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
-  load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
-  __syncthreads();
-  const int cidx = __builtin_amdgcn_readfirstlane(bx * (nth >> 6) + wave);
-  if (cidx >= ncol) return;
-  const int k2 = cidx / p.J1, je = cidx - k2 * p.J1;
-  const size_t col = cidx;
-  double fac;
-  int pol;
-  column_policy(je, k2, p.N1, p.N2, fac, pol);
-  if (!SPEC && fac == 0.0) {
-    cpx<R>* z1 = static_cast<cpx<R>*>(out) + col * N3;
-    for (int i = lane; i < N3; i += 64) z1[i] = cpx<R>{R(0), R(0)};
-    return;
-  }
-  const cpx<R>* gc = G + col * Nt;
-  for (int s = lane; s < ntt; s += 64) {
-    // slot s holds n' = s (s < ntt/2) or s - ntt; data index n = n' + Nt/2
-    const int np = s < ntt / 2 ? s : s - ntt;
-    const int n = np + Nt / 2;
-    sm.a[s] = (n >= 0 && n < Nt) ? gc[n] : cpx<R>{R(0), R(0)};
-  }
-  wave_sync();
-  fft_lds_ip<false, R, true, PPT>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, lane, 64);
-  const cpx<R>* B = sm.a;
-  const int j1 = je - p.N1 / 2;
-  const double a = double(j1) * double(j1) * p.inv_L1sq + double(k2) * double(k2) * p.inv_L2sq;
-  const double scale = SPEC ? p.scale_spec : p.scale_vol;
-  const R beta = R(p.beta);
-  for (int li = lane; li <= N3; li += 64) {
-    const int l = li - h3;
-    const LPoint<R, ARGS64> lp = lpoint<R, ARGS64>(p, a, l, scale);
-    cpx<R> H = {R(0), R(0)};
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      const int o = k - W / 2 + 1;
-      const R d = R(o) - lp.fr;
-      const R wk = wexp<R>(-beta * d * d);
-      H = H + B[pmodc(lp.q0 + o, ntt)] * wk;
-    }
-    sm.fl[li] = cmul(H, lp.ph) * lp.wgt;
-  }
-  wave_sync();
-  if constexpr (SPEC) {
-    cpx<R>* F = static_cast<cpx<R>*>(out);
-    const int N1 = p.N1, N2 = p.N2;
-    const bool direct = k2 < N2 / 2 && je < N1;
-    const bool mirror = k2 >= 1 && je >= 1;
-    const size_t rd = ((size_t)pmodc(j1, N1) * N2 + k2) * N3;
-    const size_t rm = ((size_t)pmodc(-j1, N1) * N2 + pmodc(-k2, N2)) * N3;
-    for (int li = lane; li <= N3; li += 64) {
-      const int l = li - h3;
-      if (direct && li < N3) F[rd + pmodc(l, N3)] = sm.fl[li];
-      if (mirror && li > 0) F[rm + pmodc(-l, N3)] = conjg(sm.fl[li]);
-    }
-  } else {
-    // X[slot] for the depth inverse; the transform buffer is free again
-    cpx<R>* X = sm.a;
-    const R f = R(fac);
-    for (int s = lane; s < N3; s += 64) {
-      cpx<R> v;
-      if (s == h3) {
-        const cpx<R> lo = sm.fl[0], hi = sm.fl[N3];
-        v = pol == 0 ? lo : (pol == 1 ? hi : (lo + hi) * R(0.5));
-      } else {
-        const int l = s < h3 ? s : s - N3;
-        v = sm.fl[l + h3];
-      }
-      X[s] = v * f;
-    }
-    wave_sync();
-    fft_lds_ip<true, R, true, PPT>(X, p.r_N3, 1, 1, 0, sm.tw3, lane, 64);
-    const cpx<R>* Zr = X;
-    cpx<R>* z1 = static_cast<cpx<R>*>(out) + col * N3;
-    for (int i = lane; i < N3; i += 64) z1[i] = Zr[i];
-  }
-}
-
-template <typename R, int W, bool ARGS64, bool SPEC, int PPT>
-__global__ __launch_bounds__(512) void k_column(KP p, int ncol, const cpx<R>* __restrict__ G, void* out) {
-  column_body<R, W, ARGS64, SPEC, PPT>(p, ncol, blockIdx.x, G, out);
-}
-
-// First index i in [lo, hi) with q[i] >= v (q non-decreasing).
-__device__ __forceinline__ int lower_bound_i(const int* q, int lo, int hi, int v) {
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (q[mid] < v)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-template <typename R, int W, bool ARGS64, int PPT>
-__device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap, int bx,
-                                                const cpx<R>* __restrict__ Z1, cpx<R>* __restrict__ G) {
-  extern __shared__ __align__(16) char smem[];
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int ntt = p.ntt, N3 = p.N3, Nt = p.Nt, h3 = N3 / 2;
-  ColSmem<R> sm = col_carve<R>(smem, p, wave);
-  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
-  load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
-  __syncthreads();
-  const int cidx = __builtin_amdgcn_readfirstlane(bx * (nth >> 6) + wave);
-  if (cidx >= ncol) return;
-  const int k2 = cidx / p.J1, je = cidx - k2 * p.J1;
-  const size_t col = cidx;
-  double fac;
-  int pol;
-  column_policy(je, k2, p.N1, p.N2, fac, pol);
-  cpx<R>* gc = G + col * Nt;
-  if (fac == 0.0) {
-    for (int i = lane; i < Nt; i += 64) gc[i] = cpx<R>{R(0), R(0)};
-    return;
-  }
-  const cpx<R>* zc = Z1 + col * N3;
-  for (int i = lane; i < N3; i += 64) sm.a[i] = zc[i];
-  wave_sync();
-  // transpose of the unnormalised depth inverse: forward FFT
-  fft_lds_ip<false, R, true, PPT>(sm.a, p.r_N3, 1, 1, 0, sm.tw3, lane, 64);
-  const cpx<R>* Xp = sm.a;
-  const int j1 = je - p.N1 / 2;
-  const double a = double(j1) * double(j1) * p.inv_L1sq + double(k2) * double(k2) * p.inv_L2sq;
-  const R f = R(fac);
-  const R mlo = pol == 0 ? R(1) : (pol == 1 ? R(0) : R(0.5));
-  const R mhi = pol == 1 ? R(1) : (pol == 0 ? R(0) : R(0.5));
-  for (int li = lane; li <= N3; li += 64) {
-    const int l = li - h3;
-    cpx<R> fp;
-    if (li == 0)
-      fp = Xp[h3] * (f * mlo);
-    else if (li == N3)
-      fp = Xp[h3] * (f * mhi);
-    else
-      fp = Xp[pmodc(l, N3)] * f;
-    const LPoint<R, ARGS64> lp = lpoint<R, ARGS64>(p, a, l, p.scale_vol);
-    sm.fl[li] = cmulc(fp, lp.ph) * lp.wgt;  // H'(l) = wgt * conj(ph) * F'(l)
-    sm.q0[li] = lp.q0;
-    sm.fr[li] = lp.fr;
-  }
-  wave_sync();
-  // B'[q] = sum over l whose taps cover q of phi(x_l - q) H'(l); x_l is
-  // non-decreasing in l, so the l covering q form a contiguous range.
-  cpx<R>* Bp = sm.a;
-  const R beta = R(p.beta);
-  for (int q = lane; q < ntt; q += 64) {
-    const int qc = q < ntt / 2 ? q : q - ntt;
-    cpx<R> acc = {R(0), R(0)};
-    for (int m = -mwrap; m <= mwrap; ++m) {
-      const int qv = qc + m * ntt;
-      // tap o = qv - q0 must lie in [-W/2+1, W/2]: q0 in [qv - W/2, qv + W/2 - 1]
-      const int lo = lower_bound_i(sm.q0, 0, N3 + 1, qv - W / 2);
-      const int hi = lower_bound_i(sm.q0, lo, N3 + 1, qv + W / 2);
-      for (int li = lo; li < hi; ++li) {
-        const R d = R(qv - sm.q0[li]) - sm.fr[li];
-        acc = acc + sm.fl[li] * wexp<R>(-beta * d * d);
-      }
-    }
-    Bp[q] = acc;
-  }
-  wave_sync();
-  fft_lds_ip<true, R, true, PPT>(Bp, p.r_ntt, 1, 1, 0, sm.twt, lane, 64);
-  const cpx<R>* Ap = Bp;
-  for (int n = lane; n < Nt; n += 64) {
-    const int s = pmodc(n - Nt / 2, ntt);
-    gc[n] = Ap[s];
-  }
-}
-
-template <typename R, int W, bool ARGS64, int PPT>
-__global__ __launch_bounds__(512) void k_column_adj(KP p, int ncol, int mwrap, const cpx<R>* __restrict__ Z1,
-                                                    cpx<R>* __restrict__ G) {
-  column_adj_body<R, W, ARGS64, PPT>(p, ncol, mwrap, blockIdx.x, Z1, G);
-}
-
-// ---------------------------------------------------------------- launchers
-
-// Columns (wavefronts) per workgroup: the count in 1..8 that keeps the most
-// wavefronts resident on a CU with 160 KB of LDS (the twiddles are shared).
-template <typename R>
-static int cols_per_wg(const KP& p) {
-  const size_t sh = col_shared_bytes<R>(p.ntt, p.N3), per = col_wave_bytes<R>(p.ntt, p.N3);
-  const size_t lds = 160 * 1024;
-  int best = 1;
-  size_t best_waves = 0;
-  for (int c = 1; c <= 8; ++c) {
-    const size_t wg = sh + c * per;
-    if (wg > lds) break;
-    const size_t waves = c * (lds / wg);
-    if (waves > best_waves) {
-      best_waves = waves;
-      best = c;
-    }
-  }
-  return best;
-}
-
-// Points per lane of the per-column transforms (the larger of ntt and N3 over 64).
-static int column_ppt(const KP& p) {
-  const int n = p.ntt > p.N3 ? p.ntt : p.N3;
-  const int need = (n + 63) / 64;
-  return need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
-}
-
-template <typename R, int W, bool ARGS64, int PPT>
-static hipError_t column_wp(const KP& p, const void* G, void* out, int spec, hipStream_t s) {
-  const int cpw = cols_per_wg<R>(p);
-  const int ncol = p.J1 * p.K2;
-  const size_t sh = col_shared_bytes<R>(p.ntt, p.N3) + cpw * col_wave_bytes<R>(p.ntt, p.N3);
-  dim3 grid((ncol + cpw - 1) / cpw);
-  hipError_t e = allow_smem(spec ? k_column<R, W, ARGS64, true, PPT> : k_column<R, W, ARGS64, false, PPT>, sh);
-  if (e != hipSuccess) return e;
-  if (spec)
-    hipLaunchKernelGGL((k_column<R, W, ARGS64, true, PPT>), grid, dim3(64 * cpw), sh, s, p, ncol,
-                       static_cast<const cpx<R>*>(G), out);
-  else
-    hipLaunchKernelGGL((k_column<R, W, ARGS64, false, PPT>), grid, dim3(64 * cpw), sh, s, p, ncol,
-                       static_cast<const cpx<R>*>(G), out);
-  return hipGetLastError();
-}
-
-template <typename R, int W, bool ARGS64, int PPT>
-static hipError_t column_adj_wp(const KP& p, const void* Z1, void* G, hipStream_t s) {
-  const int cpw = cols_per_wg<R>(p);
-  const int ncol = p.J1 * p.K2;
-  const size_t sh = col_shared_bytes<R>(p.ntt, p.N3) + cpw * col_wave_bytes<R>(p.ntt, p.N3);
-  dim3 grid((ncol + cpw - 1) / cpw);
-  // number of periodic images of the time grid a tap window can reach
-  const double xmax = p.cdtnt * sqrt((p.N1 / 2.0) * (p.N1 / 2.0) * p.inv_L1sq +
-                                     (p.N2 / 2.0) * (p.N2 / 2.0) * p.inv_L2sq +
-                                     (p.N3 / 2.0) * (p.N3 / 2.0) * p.bz);
-  const int mwrap = 1 + int((xmax + W) / p.ntt);
-  hipError_t e = allow_smem(k_column_adj<R, W, ARGS64, PPT>, sh);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_column_adj<R, W, ARGS64, PPT>), grid, dim3(64 * cpw), sh, s, p, ncol, mwrap,
-                     static_cast<const cpx<R>*>(Z1), static_cast<cpx<R>*>(G));
-  return hipGetLastError();
-}
-
-template <typename R, int W, bool ARGS64>
-static hipError_t column_w(const KP& p, const void* G, void* out, int spec, hipStream_t s) {
-  switch (column_ppt(p)) {
-    case 4: return column_wp<R, W, ARGS64, 4>(p, G, out, spec, s);
-    case 8: return column_wp<R, W, ARGS64, 8>(p, G, out, spec, s);
-    case 16: return column_wp<R, W, ARGS64, 16>(p, G, out, spec, s);
-    case 32: return column_wp<R, W, ARGS64, 32>(p, G, out, spec, s);
-    default: return column_wp<R, W, ARGS64, 64>(p, G, out, spec, s);
-  }
-}
-
-template <typename R, int W, bool ARGS64>
-static hipError_t column_adj_w(const KP& p, const void* Z1, void* G, hipStream_t s) {
-  switch (column_ppt(p)) {
-    case 4: return column_adj_wp<R, W, ARGS64, 4>(p, Z1, G, s);
-    case 8: return column_adj_wp<R, W, ARGS64, 8>(p, Z1, G, s);
-    case 16: return column_adj_wp<R, W, ARGS64, 16>(p, Z1, G, s);
-    case 32: return column_adj_wp<R, W, ARGS64, 32>(p, Z1, G, s);
-    default: return column_adj_wp<R, W, ARGS64, 64>(p, Z1, G, s);
-  }
-}
-
-template <typename R, bool ARGS64>
-static hipError_t column_a(const KP& p, const void* in, void* out, int spec, hipStream_t s, bool adj) {
-  switch (p.W) {
-#define NEDNER_CW(WV) \
-  case WV:            \
-    return adj ? column_adj_w<R, WV, ARGS64>(p, in, out, s) : column_w<R, WV, ARGS64>(p, in, out, spec, s);
-    NEDNER_CW(2)
-    NEDNER_CW(4)
-    NEDNER_CW(6)
-    NEDNER_CW(8)
-    NEDNER_CW(10)
-    NEDNER_CW(12)
-    NEDNER_CW(14)
-    NEDNER_CW(16)
-#undef NEDNER_CW
-    default:
-      return hipErrorInvalidValue;
-  }
-}
+extern template hipError_t column_a<double, true>(const KP&, const void*, void*, int, hipStream_t, bool);
+extern template hipError_t column_many_a<double, true>(const KP&, int, const BatchProb*, const WorkList&, int, size_t,
+                                                   hipStream_t);
+extern template hipError_t column_a<float, true>(const KP&, const void*, void*, int, hipStream_t, bool);
+extern template hipError_t column_many_a<float, true>(const KP&, int, const BatchProb*, const WorkList&, int, size_t,
+                                                   hipStream_t);
+extern template hipError_t column_a<float, false>(const KP&, const void*, void*, int, hipStream_t, bool);
+extern template hipError_t column_many_a<float, false>(const KP&, int, const BatchProb*, const WorkList&, int, size_t,
+                                                   hipStream_t);
 
 static hipError_t column_dispatch(const KP& p, const void* in, void* out, int spec, hipStream_t s, bool adj) {
   switch (p.prec) {
@@ -454,59 +20,6 @@ static hipError_t column_dispatch(const KP& p, const void* in, void* out, int sp
     case PREC_FP32P: return column_a<float, false>(p, in, out, spec, s, adj);
     default: return column_a<float, true>(p, in, out, spec, s, adj);
   }
-}
-
-// ---------------------------------------------------------------- batched
-template <typename R, int W, bool ARGS64, int PPT>
-__global__ __launch_bounds__(512) void k_column_many(const BatchProb* __restrict__ bp, WorkList wl) {
-  work_loop(wl, [&](int prob, int local) {
-    const BatchProb& B = bp[prob];
-    const KP& p = B.kp;
-    column_body<R, W, ARGS64, false, PPT>(p, p.J1 * p.K2, local, static_cast<const cpx<R>*>(B.b0), B.b1);
-  });
-}
-
-template <typename R, int W, bool ARGS64, int PPT>
-static hipError_t column_many_wp(const BatchProb* bp, const WorkList& wl, int cpw, size_t smem, hipStream_t s) {
-  if (wl.total <= 0) return hipSuccess;
-  auto k = k_column_many<R, W, ARGS64, PPT>;
-  hipError_t e = allow_smem(k, smem);
-  if (e != hipSuccess) return e;
-  int per_cu = 0, dev = 0, cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64 * cpw, smem) !=
-          hipSuccess || per_cu < 1)
-    per_cu = 1;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int grid = (int)std::min<long>((long)per_cu * cus, wl.total);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * cpw), smem, s, bp, wl);
-  return hipGetLastError();
-}
-
-template <typename R, bool ARGS64>
-static hipError_t column_many_a(const KP& p0, int ppt, const BatchProb* bp, const WorkList& wl, int cpw,
-                                size_t smem, hipStream_t s) {
-#define NEDNER_CMP(WV)                                                                   \
-  case WV:                                                                               \
-    switch (ppt) {                                                                       \
-      case 4: return column_many_wp<R, WV, ARGS64, 4>(bp, wl, cpw, smem, s);             \
-      case 8: return column_many_wp<R, WV, ARGS64, 8>(bp, wl, cpw, smem, s);             \
-      case 16: return column_many_wp<R, WV, ARGS64, 16>(bp, wl, cpw, smem, s);           \
-      case 32: return column_many_wp<R, WV, ARGS64, 32>(bp, wl, cpw, smem, s);           \
-      default: return column_many_wp<R, WV, ARGS64, 64>(bp, wl, cpw, smem, s);           \
-    }
-  switch (p0.W) {
-    NEDNER_CMP(2)
-    NEDNER_CMP(4)
-    NEDNER_CMP(6)
-    NEDNER_CMP(8)
-    NEDNER_CMP(10)
-    NEDNER_CMP(12)
-    NEDNER_CMP(14)
-    NEDNER_CMP(16)
-    default: return hipErrorInvalidValue;
-  }
-#undef NEDNER_CMP
 }
 
 // cpw columns per workgroup and `smem` bytes of LDS (the maxima over the batch);
@@ -523,7 +36,8 @@ hipError_t launch_column_many(const KP& p0, const BatchProb* bp, const WorkList&
 
 // host helpers for the batched plan
 size_t column_wave_bytes_host(const KP& p) {
-  return p.prec == PREC_FP64 ? col_wave_bytes<double>(p.ntt, p.N3) : col_wave_bytes<float>(p.ntt, p.N3);
+  return p.prec == PREC_FP64 ? col_wave_bytes<double>(p.ntt, p.N3, false)
+                             : col_wave_bytes<float>(p.ntt, p.N3, false);
 }
 size_t column_shared_bytes_host(const KP& p) {
   return p.prec == PREC_FP64 ? col_shared_bytes<double>(p.ntt, p.N3) : col_shared_bytes<float>(p.ntt, p.N3);

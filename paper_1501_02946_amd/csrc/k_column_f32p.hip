@@ -1,0 +1,10 @@
+// NER column kernels instantiated for FP32 throughout (fp32_plain).
+#include "k_column_impl.hpp"
+
+namespace nedner {
+
+template hipError_t column_a<float, false>(const KP&, const void*, void*, int, hipStream_t, bool);
+template hipError_t column_many_a<float, false>(const KP&, int, const BatchProb*, const WorkList&, int, size_t,
+                                            hipStream_t);
+
+}  // namespace nedner

@@ -22,11 +22,6 @@
 
 namespace nedner {
 
-__device__ __forceinline__ int pmodp(int a, int n) {
-  int r = a % n;
-  return r < 0 ? r + n : r;
-}
-
 template <typename R>
 struct Smem {
   cpx<R>* tw;
@@ -67,20 +62,21 @@ __device__ __forceinline__ void lat_a_body(const KP& p, int TB, int bx, int by, 
   const int q1 = by, pb = bx * TB, npairs = p.Nt / 2;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n2), n, tid, nth);
   const R* src = U + (size_t)q1 * n * p.Nt;
-  for (int i = tid; i < n * TB; i += nth) {
-    const int q2 = i / TB, pp = i - q2 * TB, pr = pb + pp;
+  const int lsh = __builtin_ctz(TB);
+  stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
+    const int q2 = i >> lsh, pr = pb + (i & (TB - 1));
     cpx<R> z = {R(0), R(0)};
     if (pr < npairs) z = *reinterpret_cast<const cpx<R>*>(src + (size_t)q2 * p.Nt + 2 * pr);
-    sm.a[i] = z;
-  }
+    return z;
+  });
   __syncthreads();
   cpx<R>* Z = pass_fft<false, R, IP>(sm, p.r_n2, TB, tid, nth);
   cpx<R>* dst = V + (size_t)q1 * p.K2 * p.Nt;
   for (int i = tid; i < p.K2 * TB; i += nth) {
-    const int k = i / TB, pp = i - k * TB, pr = pb + pp;
+    const int k = i >> lsh, pp = i & (TB - 1), pr = pb + pp;
     if (pr >= npairs) continue;
     const cpx<R> a = Z[k * TB + pp];
-    const cpx<R> b = Z[((n - k) % n) * TB + pp];
+    const cpx<R> b = Z[(k == 0 ? 0 : n - k) * TB + pp];
     const cpx<R> X = {(a.x + b.x) * R(0.5), (a.y - b.y) * R(0.5)};
     const cpx<R> Y = {(a.y + b.y) * R(0.5), (b.x - a.x) * R(0.5)};
     dst[(size_t)k * p.Nt + 2 * pr] = X;
@@ -102,21 +98,23 @@ __device__ __forceinline__ void lat_b_body(const KP& p, int TB, int bx, int by, 
   Smem<R> sm = carve<R>(smem, n, TB);
   const int k2 = by, nb = bx * TB, Nt = p.Nt;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n1), n, tid, nth);
-  for (int i = tid; i < n * TB; i += nth) {
-    const int q1 = i / TB, t = i - q1 * TB, nn = nb + t;
+  const int lsh = __builtin_ctz(TB);
+  stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
+    const int q1 = i >> lsh, nn = nb + (i & (TB - 1));
     cpx<R> z = {R(0), R(0)};
     if (nn < Nt) z = V[((size_t)q1 * p.K2 + k2) * Nt + nn];
-    sm.a[i] = z;
-  }
+    return z;
+  });
   __syncthreads();
   cpx<R>* Z = pass_fft<false, R, IP>(sm, p.r_n1, TB, tid, nth);
   const R* d1 = static_cast<const R*>(p.dec1);
   const R* dt = static_cast<const R*>(p.dect);
   const R d2 = static_cast<const R*>(p.dec2)[k2];
   for (int i = tid; i < p.J1 * TB; i += nth) {
-    const int je = i / TB, t = i - je * TB, nn = nb + t;
+    const int je = i >> lsh, t = i & (TB - 1), nn = nb + t;
     if (nn >= Nt) continue;
-    const int k1 = pmodp(je - p.N1 / 2, n);
+    const int j1 = je - p.N1 / 2;
+    const int k1 = j1 < 0 ? j1 + n : j1;
     G[((size_t)k2 * p.J1 + je) * Nt + nn] = Z[k1 * TB + t] * (d1[je] * d2 * dt[nn]);
   }
 }
@@ -136,21 +134,22 @@ __device__ __forceinline__ void pass_c_body(const KP& p, int TB, int bx, int by,
   const int k2 = by, ib = bx * TB, N3 = p.N3;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N1), n, tid, nth);
   const cpx<R>* src = Z1 + (size_t)k2 * p.J1 * N3;
-  for (int i = tid; i < n * TB; i += nth) {
-    const int s = i / TB, t = i - s * TB, i3 = ib + t;
+  const int lsh = __builtin_ctz(TB);
+  stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
+    const int s = i >> lsh, i3 = ib + (i & (TB - 1));
     cpx<R> z = {R(0), R(0)};
     if (i3 < N3) {
       const int j1 = s < n / 2 ? s : s - n;
       z = src[(size_t)(j1 + n / 2) * N3 + i3];
       if (s == n / 2) z = z + src[(size_t)n * N3 + i3];
     }
-    sm.a[i] = z;
-  }
+    return z;
+  });
   __syncthreads();
   cpx<R>* Z = pass_fft<true, R, IP>(sm, p.r_N1, TB, tid, nth);
   cpx<R>* dst = Z2 + (size_t)k2 * n * N3;
   for (int i = tid; i < n * TB; i += nth) {
-    const int i1 = i / TB, t = i - i1 * TB, i3 = ib + t;
+    const int i1 = i >> lsh, t = i & (TB - 1), i3 = ib + t;
     if (i3 < N3) dst[(size_t)i1 * N3 + i3] = Z[i];
   }
 }
@@ -169,8 +168,9 @@ __device__ __forceinline__ void pass_d_body(const KP& p, int TB, int bx, int by,
   Smem<R> sm = carve<R>(smem, n, TB);
   const int i1 = by, pb = bx * TB, N3 = p.N3, npairs = N3 / 2, h = n / 2;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N2), n, tid, nth);
-  for (int i = tid; i < n * TB; i += nth) {
-    const int k = i / TB, pp = i - k * TB, pr = pb + pp;
+  const int lsh = __builtin_ctz(TB);
+  stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
+    const int k = i >> lsh, pr = pb + (i & (TB - 1));
     cpx<R> c = {R(0), R(0)};
     if (pr < npairs) {
       const int kk = k <= h ? k : n - k;
@@ -183,13 +183,13 @@ __device__ __forceinline__ void pass_d_body(const KP& p, int TB, int bx, int by,
       else
         c = {za.x + zb.y, zb.x - za.y};
     }
-    sm.a[i] = c;
-  }
+    return c;
+  });
   __syncthreads();
   cpx<R>* Z = pass_fft<true, R, IP>(sm, p.r_N2, TB, tid, nth);
   R* dst = vol + (size_t)i1 * n * N3;
   for (int i = tid; i < n * TB; i += nth) {
-    const int i2 = i / TB, pp = i - i2 * TB, pr = pb + pp;
+    const int i2 = i >> lsh, pp = i & (TB - 1), pr = pb + pp;
     if (pr < npairs) *reinterpret_cast<cpx<R>*>(dst + (size_t)i2 * N3 + 2 * pr) = Z[i];
   }
 }
@@ -211,19 +211,20 @@ __device__ __forceinline__ void adj_d_body(const KP& p, int TB, int bx, int by, 
   const int i1 = by, pb = bx * TB, N3 = p.N3, npairs = N3 / 2, h = n / 2;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N2), n, tid, nth);
   const R* src = vol + (size_t)i1 * n * N3;
-  for (int i = tid; i < n * TB; i += nth) {
-    const int i2 = i / TB, pp = i - i2 * TB, pr = pb + pp;
+  const int lsh = __builtin_ctz(TB);
+  stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
+    const int i2 = i >> lsh, pr = pb + (i & (TB - 1));
     cpx<R> z = {R(0), R(0)};
     if (pr < npairs) z = *reinterpret_cast<const cpx<R>*>(src + (size_t)i2 * N3 + 2 * pr);
-    sm.a[i] = z;
-  }
+    return z;
+  });
   __syncthreads();
   cpx<R>* Z = pass_fft<false, R, IP>(sm, p.r_N2, TB, tid, nth);
   for (int i = tid; i < (h + 1) * TB; i += nth) {
-    const int k = i / TB, pp = i - k * TB, pr = pb + pp;
+    const int k = i >> lsh, pp = i & (TB - 1), pr = pb + pp;
     if (pr >= npairs) continue;
     const cpx<R> a = Z[k * TB + pp];
-    const cpx<R> b = Z[((n - k) % n) * TB + pp];
+    const cpx<R> b = Z[(k == 0 ? 0 : n - k) * TB + pp];
     const R al = (k == 0 || k == h) ? R(0.5) : R(1);
     const cpx<R> Va = {(a.x + b.x) * al, (a.y - b.y) * al};
     const cpx<R> Vb = {(a.y + b.y) * al, (b.x - a.x) * al};
@@ -248,19 +249,21 @@ __device__ __forceinline__ void adj_c_body(const KP& p, int TB, int bx, int by, 
   const int k2 = by, ib = bx * TB, N3 = p.N3;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N1), n, tid, nth);
   const cpx<R>* src = Z2 + (size_t)k2 * n * N3;
-  for (int i = tid; i < n * TB; i += nth) {
-    const int i1 = i / TB, t = i - i1 * TB, i3 = ib + t;
+  const int lsh = __builtin_ctz(TB);
+  stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
+    const int i1 = i >> lsh, i3 = ib + (i & (TB - 1));
     cpx<R> z = {R(0), R(0)};
     if (i3 < N3) z = src[(size_t)i1 * N3 + i3];
-    sm.a[i] = z;
-  }
+    return z;
+  });
   __syncthreads();
   cpx<R>* Z = pass_fft<false, R, IP>(sm, p.r_N1, TB, tid, nth);
   cpx<R>* dst = Z1 + (size_t)k2 * p.J1 * N3;
   for (int i = tid; i < p.J1 * TB; i += nth) {
-    const int je = i / TB, t = i - je * TB, i3 = ib + t;
+    const int je = i >> lsh, t = i & (TB - 1), i3 = ib + t;
     if (i3 >= N3) continue;
-    const int s = pmodp(je - n / 2, n);
+    const int j1 = je - n / 2;
+    const int s = j1 < 0 ? j1 + n : j1;
     dst[(size_t)je * N3 + i3] = Z[s * TB + t];
   }
 }
@@ -282,20 +285,21 @@ __device__ __forceinline__ void adj_b_body(const KP& p, int TB, int bx, int by, 
   const R* d1 = static_cast<const R*>(p.dec1);
   const R* dt = static_cast<const R*>(p.dect);
   const R d2 = static_cast<const R*>(p.dec2)[k2];
-  for (int i = tid; i < n * TB; i += nth) {
-    const int k1 = i / TB, t = i - k1 * TB, nn = nb + t;
+  const int lsh = __builtin_ctz(TB);
+  stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
+    const int k1 = i >> lsh, nn = nb + (i & (TB - 1));
     cpx<R> z = {R(0), R(0)};
     const int j1 = k1 < n / 2 ? k1 : k1 - n;
     if (nn < Nt && j1 >= -h1 && j1 <= h1) {
       const int je = j1 + h1;
       z = G[((size_t)k2 * p.J1 + je) * Nt + nn] * (d1[je] * d2 * dt[nn]);
     }
-    sm.a[i] = z;
-  }
+    return z;
+  });
   __syncthreads();
   cpx<R>* Z = pass_fft<true, R, IP>(sm, p.r_n1, TB, tid, nth);
   for (int i = tid; i < n * TB; i += nth) {
-    const int q1 = i / TB, t = i - q1 * TB, nn = nb + t;
+    const int q1 = i >> lsh, t = i & (TB - 1), nn = nb + t;
     if (nn < Nt) V[((size_t)q1 * p.K2 + k2) * Nt + nn] = Z[i];
   }
 }
@@ -315,8 +319,9 @@ __device__ __forceinline__ void adj_a_body(const KP& p, int TB, int bx, int by, 
   const int q1 = by, pb = bx * TB, npairs = p.Nt / 2, h2 = p.N2 / 2;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n2), n, tid, nth);
   const cpx<R>* src = V + (size_t)q1 * p.K2 * p.Nt;
-  for (int i = tid; i < n * TB; i += nth) {
-    const int k = i / TB, pp = i - k * TB, pr = pb + pp;
+  const int lsh = __builtin_ctz(TB);
+  stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
+    const int k = i >> lsh, pr = pb + (i & (TB - 1));
     cpx<R> c = {R(0), R(0)};
     if (pr < npairs) {
       if (k == 0) {
@@ -331,13 +336,13 @@ __device__ __forceinline__ void adj_a_body(const KP& p, int TB, int bx, int by, 
         c = {(a.x + b.y) * R(0.5), (b.x - a.y) * R(0.5)};
       }
     }
-    sm.a[i] = c;
-  }
+    return c;
+  });
   __syncthreads();
   cpx<R>* Z = pass_fft<true, R, IP>(sm, p.r_n2, TB, tid, nth);
   R* dst = U + (size_t)q1 * n * p.Nt;
   for (int i = tid; i < n * TB; i += nth) {
-    const int q2 = i / TB, pp = i - q2 * TB, pr = pb + pp;
+    const int q2 = i >> lsh, pp = i & (TB - 1), pr = pb + pp;
     if (pr < npairs) *reinterpret_cast<cpx<R>*>(dst + (size_t)q2 * p.Nt + 2 * pr) = Z[i];
   }
 }
@@ -350,6 +355,15 @@ __global__ __launch_bounds__(512) void k_adj_a(KP p, int TB, const cpx<R>* __res
 
 // ---------------------------------------------------------------- launchers
 
+// Threads of a single-plan pass: in place, a tile of n * TB points needs no
+// more than one thread per 8 points, so short transforms run with fewer
+// (whole) wavefronts instead of idling half of them in every stage.
+static int pass_threads_for(const KP& p, int n, int TB) {
+  if (!p.pass_ip) return p.pass_threads;
+  const int need = ((n * TB / 8 + 63) / 64) * 64;
+  return std::min(p.pass_threads, std::max(64, need));
+}
+
 template <typename R>
 static size_t smem_for(int n, int TB, bool ip) {
   return (size_t)n * sizeof(cpx<R>) * ((ip ? 1 : 2) * (size_t)TB + 1);
@@ -361,15 +375,16 @@ static size_t smem_for(int n, int TB, bool ip) {
     const int n = (NLEN);                                                                       \
     const int TB = pass_lines_for(p, n, (int)sizeof(cpx<R>));                                   \
     const bool ip = p.pass_ip != 0;                                                             \
+    const int nth = pass_threads_for(p, n, TB);                                                 \
     const size_t sh = smem_for<R>(n, TB, ip);                                                   \
     dim3 grid(((GYLINES) + TB - 1) / TB, (GX));                                                 \
     hipError_t e = ip ? allow_smem(KERNEL<R, true>, sh) : allow_smem(KERNEL<R, false>, sh);     \
     if (e != hipSuccess) return e;                                                              \
     if (ip)                                                                                     \
-      hipLaunchKernelGGL((KERNEL<R, true>), grid, dim3(p.pass_threads), sh, s, p, TB,           \
+      hipLaunchKernelGGL((KERNEL<R, true>), grid, dim3(nth), sh, s, p, TB,                      \
                          static_cast<const IN_T*>(in), static_cast<OUT_T*>(out));               \
     else                                                                                        \
-      hipLaunchKernelGGL((KERNEL<R, false>), grid, dim3(p.pass_threads), sh, s, p, TB,          \
+      hipLaunchKernelGGL((KERNEL<R, false>), grid, dim3(nth), sh, s, p, TB,                     \
                          static_cast<const IN_T*>(in), static_cast<OUT_T*>(out));               \
     return hipGetLastError();                                                                   \
   }

@@ -93,16 +93,17 @@ __device__ __forceinline__ void spread_body(const KP& p, int bx, const int* __re
   constexpr bool PW = sizeof(WT) == 4;
   const int lane = threadIdx.x & 63;
   // XCD-aware order: the hardware deals workgroups round-robin to the 8 XCDs;
-  // give each XCD a contiguous run of column groups (of one segment and time
-  // chunk) so that the sensors shared by neighbouring columns stay in its L2.
+  // give each XCD a contiguous run of (time chunk, column group) pairs of one
+  // segment, so that the lists and weights the time chunks of a column share,
+  // and the sensors neighbouring columns share, stay in its L2.
   const int ncg = (p.n2 + 3) / 4;
   const int G = ncg * p.nseg * p.nchunk;
   const int per = (G + 7) / 8;
   const int L = (bx & 7) * per + (bx >> 3);
   if (L >= G) return;
-  const int cgi = L % ncg;
-  const int seg = (L / ncg) % p.nseg;
-  const int chunk = L / (ncg * p.nseg);
+  const int chunk = L % p.nchunk;
+  const int cgi = (L / p.nchunk) % ncg;
+  const int seg = L / (p.nchunk * ncg);
   const int q2 = __builtin_amdgcn_readfirstlane(cgi * 4 + (threadIdx.x >> 6));
   if (q2 >= p.n2) return;
   const int S0 = seg * p.S;
@@ -222,13 +223,143 @@ __device__ __forceinline__ void spread_body(const KP& p, int bx, const int* __re
   }
 }
 
+// Staged variant. Samples are staged in batches of BE entries: while the wave accumulates the
+// entries of one batch, whose samples sit in this lane's LDS slots, the samples
+// of the next batch are in flight into registers; at the batch boundary they
+// go to LDS and the loads of the batch after are issued. A wave thus waits on
+// global memory once per batch, for loads issued a whole batch earlier. Each
+// lane reads back only what it wrote, so no barrier is needed.
+template <int W, int TT, typename R, typename WT, typename A, bool VEC>
+__device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const int* __restrict__ cellbeg,
+                                                   const int* __restrict__ em, const WT* __restrict__ ew,
+                                                   const WT* __restrict__ w1t, const R* __restrict__ g,
+                                                   R* __restrict__ U) {
+  constexpr int BE = sizeof(R) == 4 ? 4 : 2;
+  __shared__ R stage[4][BE * 64 * TT];
+  const int lane = threadIdx.x & 63;
+  R* __restrict__ stg = stage[threadIdx.x >> 6] + lane * TT;
+  const int ncg = (p.n2 + 3) / 4;
+  const int G = ncg * p.nseg * p.nchunk;
+  const int per = (G + 7) / 8;
+  const int L = (bx & 7) * per + (bx >> 3);
+  if (L >= G) return;
+  const int chunk = L % p.nchunk;
+  const int cgi = (L / p.nchunk) % ncg;
+  const int seg = L / (p.nchunk * ncg);
+  const int q2 = __builtin_amdgcn_readfirstlane(cgi * 4 + (threadIdx.x >> 6));
+  if (q2 >= p.n2) return;
+  const int S0 = seg * p.S;
+  const int S1 = min(S0 + p.S, p.n1);
+  const int Vstart = S0 - W / 2;
+  const int Vend = S1 + W / 2 - 2;
+  const int* __restrict__ cb = cellbeg + (size_t)(q2 * p.nseg + seg) * p.CB;
+  const int Nt = p.Nt;
+  const int tb = chunk * 64 * TT + lane * TT;
+  const bool lane_ok = tb < Nt;
+  const int toff = lane_ok ? tb : 0;
+
+  A acc[W][TT];
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+#pragma unroll
+    for (int t = 0; t < TT; ++t) acc[k][t] = A(0);
+
+  int e = cb[0];
+  const int eall = cb[Vend - Vstart + 1];
+  // samples of entries nb .. nb+BE-1, in flight, and the sensor indices of
+  // the batch after them, read a batch ahead; the table of sensor indices is
+  // padded past its end, so every index read here is valid
+  R nx[BE][TT];
+  int mp[BE];
+  auto issue = [&](int e0) {
+    if (e0 < eall) {
+#pragma unroll
+      for (int j = 0; j < BE; ++j) load_tt<TT>(nx[j], g + (size_t)mp[j] * Nt + toff, TT, VEC);
+    }
+#pragma unroll
+    for (int j = 0; j < BE; ++j) mp[j] = em[e0 + BE + j];
+  };
+  int nb = e;
+#pragma unroll
+  for (int j = 0; j < BE; ++j) mp[j] = em[nb + j];
+  issue(nb);
+  // scalar pipeline: the first-axis weights of the sensor of the next entry
+  // and that entry's second-axis weight are read one entry ahead, the sensor
+  // index two entries ahead (the index and weight tables are padded past
+  // their end, so every read ahead is valid)
+  WT wn[W];
+  {
+    const int m0 = em[e];
+#pragma unroll
+    for (int k = 0; k < W; ++k) wn[k] = w1t[(size_t)m0 * W + k];
+  }
+  WT w2n = ew[e];
+  int mn = em[e + 1];
+  for (int c0 = floor_div(Vstart, W) * W; c0 <= Vend; c0 += W) {
+#pragma unroll
+    for (int r = 0; r < W; ++r) {
+      const int V = c0 + r;
+      if (V < Vstart || V > Vend) continue;
+      const int stop = cb[V - Vstart + 1];
+      while (e < stop) {
+        if (e == nb) {
+#pragma unroll
+          for (int j = 0; j < BE; ++j)
+#pragma unroll
+            for (int t = 0; t < TT; ++t) stg[j * 64 * TT + t] = nx[j][t];
+          nb += BE;
+          issue(nb);
+        }
+        const int j = e - (nb - BE);
+        A gd[TT];
+#pragma unroll
+        for (int t = 0; t < TT; ++t) gd[t] = A(stg[j * 64 * TT + t]);
+        WT wc[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) wc[k] = wn[k];
+        const WT w2c = w2n;
+        // keep the next entry's loads behind the wait for this entry's data:
+        // a scalar load issued before it would be waited for as well
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < W; ++k) wn[k] = w1t[(size_t)mn * W + k];
+        w2n = ew[e + 1];
+        mn = em[e + 2];
+#pragma unroll
+        for (int t = 0; t < TT; ++t) gd[t] *= A(w2c);
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const A w = A(wc[k]);
+#pragma unroll
+          for (int t = 0; t < TT; ++t) acc[(r + k + W / 2 + 1) % W][t] += w * gd[t];
+        }
+        ++e;
+      }
+      const int slot = (r + W / 2 + 1) % W;
+      const int Q = V - W / 2 + 1;
+      if (Q >= S0 && Q < S1 && lane_ok) {
+        R o[TT];
+#pragma unroll
+        for (int t = 0; t < TT; ++t) o[t] = R(acc[slot][t]);
+        store_tt<TT>(U + ((size_t)Q * p.n2 + q2) * Nt + tb, o, TT, VEC);
+      }
+#pragma unroll
+      for (int t = 0; t < TT; ++t) acc[slot][t] = A(0);
+    }
+  }
+}
+
+// PD == 2: the two-deep register pipeline; PD == 1: samples staged through LDS.
 template <int W, int TT, typename R, typename WT, typename A, bool VEC, int PD>
 __global__ __launch_bounds__(256) void k_spread(KP p, const int* __restrict__ cellbeg,
                                                 const int* __restrict__ em,
                                                 const WT* __restrict__ ew,
                                                 const WT* __restrict__ w1t,
                                                 const R* __restrict__ g, R* __restrict__ U) {
-  spread_body<W, TT, R, WT, A, VEC, PD>(p, blockIdx.x, cellbeg, em, ew, w1t, g, U);
+  if constexpr (PD == 2)
+    spread_body<W, TT, R, WT, A, VEC, PD>(p, blockIdx.x, cellbeg, em, ew, w1t, g, U);
+  else
+    spread_body_staged<W, TT, R, WT, A, VEC>(p, blockIdx.x, cellbeg, em, ew, w1t, g, U);
 }
 
 // Transpose of the spreading: g'[m][n] = sum_taps s_m phi(q1-u1) phi(q2-u2) U'[q1][q2][n].
@@ -364,10 +495,16 @@ __global__ __launch_bounds__(256) void k_spread_many(const BatchProb* __restrict
   work_loop(wl, [&](int prob, int local) {
     const BatchProb& B = bp[prob];
     const KP& p = B.kp;
-    spread_body<W, TT, R, WT, A, VEC, PD>(p, local, p.cellbeg, p.ent_m,
-                                          static_cast<const WT*>(p.ent_w2),
-                                          static_cast<const WT*>(p.w1), static_cast<const R*>(B.g),
-                                          static_cast<R*>(B.b0));
+    if constexpr (PD == 2)
+      spread_body<W, TT, R, WT, A, VEC, PD>(p, local, p.cellbeg, p.ent_m,
+                                            static_cast<const WT*>(p.ent_w2),
+                                            static_cast<const WT*>(p.w1), static_cast<const R*>(B.g),
+                                            static_cast<R*>(B.b0));
+    else
+      spread_body_staged<W, TT, R, WT, A, VEC>(p, local, p.cellbeg, p.ent_m,
+                                               static_cast<const WT*>(p.ent_w2),
+                                               static_cast<const WT*>(p.w1), static_cast<const R*>(B.g),
+                                               static_cast<R*>(B.b0));
   });
 }
 

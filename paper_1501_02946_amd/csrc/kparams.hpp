@@ -29,7 +29,7 @@ struct KP {
   int CB;         // stride of the per-(column, segment) cell offset table: S + W
   int nchunk;     // time chunks of 64*TT samples
   int prec;       // Prec
-  int spread_pd;  // software pipeline depth of the spreading sweep (1 or 2)
+  int spread_pd;  // spreading sweep: 1 = samples staged through LDS, 2 = two-deep register pipeline
   int wide_w;     // FP32C: 8-byte first-axis weights (fetched at use) instead of 4-byte
   int pass_lines; // FFT passes: lines per workgroup (power of two, upper bound)
   int pass_threads; // FFT passes: threads per workgroup (multiple of 64, <= 512)
@@ -64,6 +64,11 @@ struct KP {
   const void* tw_N3;
   Radices r_n1, r_n2, r_ntt, r_N1, r_N2, r_N3;
 };
+
+// The per-column transform buffer of the NER kernel holds max(ntt, N3)
+// points plus COL_EXT periodic copies of its first points, so that a tap
+// window never wraps (W <= COL_EXT).
+constexpr int COL_EXT = 16;
 
 // Workspace buffers of one execute (device pointers).
 struct Bufs {
