@@ -10,6 +10,7 @@ resident batch of synthetic sensor data. Prints ONE JSON line:
                timed live with HIP events on the execute stream
   cpu_baseline the FP64 oracle timed on the host on the same workload
   fp64_plain   the same operator in FP64 on the GPU, and the FP32 speedup
+  kaiser_bessel_w8  the same workload with the Kaiser-Bessel window at 8 taps
 
 Inputs: 128x128 jittered sensors (+/-0.45 pitch), 512 samples, 10 random balls
 and 1 % noise, output 128x128x256 (the FP32-vs-plain comparison workload).
@@ -270,6 +271,8 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp32_plain", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-kb", action="store_true",
+                    help="skip the Kaiser-Bessel (8-tap) leg timed beside the headline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
@@ -361,6 +364,19 @@ def main(argv=None):
         del p64
     else:
         vol64 = None
+    volkb = None
+    if not a.no_kb:
+        # the paper's window choice: Kaiser-Bessel, 8 taps per axis instead of 12
+        pkb = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0,
+                     precision=a.precision, w=8, window="kaiser_bessel")
+        okb = torch.empty((p.n1, p.n2, p.n3), dtype=plan.dtype, device=plan.device)
+        mskb, _ = time_steps(torch, pkb, g, okb, a.steps, a.warmup)
+        _, stkb = time_steps(torch, pkb, g, okb, a.steps, 1, profile=True)
+        res["kaiser_bessel_w8"] = dict(ms_per_step=round(mskb, 5),
+                                       value=round(points / (mskb / 1e3) / 1e6, 2),
+                                       stages_ms={k: round(v, 5) for k, v in stkb.items()})
+        volkb = okb.cpu().numpy()
+        del pkb
     if not a.no_cpu_baseline:
         vref, cb = cpu_baseline(p)
         res["cpu_baseline"] = cb
@@ -368,6 +384,9 @@ def main(argv=None):
         res["rel_l2_vs_oracle"] = float(np.linalg.norm(vol.astype(np.float64) - vref) / nrm)
         if vol64 is not None:
             res["fp64_plain"]["rel_l2_vs_oracle"] = float(np.linalg.norm(vol64 - vref) / nrm)
+        if volkb is not None:
+            res["kaiser_bessel_w8"]["rel_l2_vs_oracle"] = float(
+                np.linalg.norm(volkb.astype(np.float64) - vref) / nrm)
     else:
         res["cpu_baseline"] = None
     print(json.dumps(res), flush=True)

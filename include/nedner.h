@@ -78,6 +78,21 @@ typedef enum {
   NEDNER_FP32_PLAIN = 3         /* float everywhere, arguments included */
 } nedner_precision;
 
+/* Interpolation window of the spreading (eq. (10)) and of the NER gather
+   (eq. (8)), the same on all three axes, W taps per axis around each point.
+   Gaussian: phi(x) = exp(-beta x^2), beta = pi (sigma - 1/2) / (sigma W/2) / tau_scale
+     (Greengard and Lee, SIAM Rev. 46 (2004)), phihat(xi) = sqrt(pi/beta) exp(-pi^2 xi^2/beta).
+   Kaiser-Bessel (the paper's window, Sec. 3): phi(x) = I0(beta sqrt(1 - (2x/W)^2)) for
+     |x| < W/2, beta = pi sqrt((W/sigma)^2 (sigma - 1/2)^2 - 0.8) (Beatty, Nishimura and
+     Pauly, IEEE TMI 24 (2005)), phihat(xi) = W sinh(z)/z with z = sqrt(beta^2 - (pi W xi)^2)
+     (sin(|z|)/|z| past the cut-off). It reaches a given accuracy with fewer taps;
+     it is built for w = 4..12 (NEDNER_E_UNSUPPORTED otherwise).
+   x is in oversampled grid units, xi in cycles per grid unit. */
+typedef enum {
+  NEDNER_WINDOW_GAUSSIAN = 0,
+  NEDNER_WINDOW_KAISER_BESSEL = 1
+} nedner_window;
+
 typedef enum {
   NEDNER_VOLUME_REAL = 0,       /* the image f, [n1][n2][n3] real */
   NEDNER_SPECTRUM_COMPLEX = 1,  /* F(j,l), [n1][n2][n3] complex, FFT order */
@@ -107,6 +122,7 @@ typedef struct {
   uint32_t flags;       /* NEDNER_* flags */
   int32_t rows_per_wave;   /* spreading sweep length; 0 = automatic */
   int32_t time_per_lane;   /* time samples per lane in spreading (1, 2, 4); 0 = automatic */
+  int32_t window;          /* nedner_window (default Gaussian); tau_scale applies to the Gaussian */
 } nedner_desc;
 
 /* Sizes a descriptor implies; filled by nedner_query (host only, no HIP). */
@@ -119,7 +135,7 @@ typedef struct {
   int32_t pad0;
   size_t workspace_bytes;        /* device workspace an execute needs */
   size_t table_bytes;            /* device tables the plan allocates */
-  double beta;                   /* Gaussian exponent: phi(x) = exp(-beta x^2), x in grid units */
+  double beta;                   /* window parameter beta (see nedner_window) */
   double max_abs_theta;          /* max |omega| dt over the mode set (alias check: < pi) */
   int64_t list_entries;          /* (sensor, column) pairs in the spreading lists */
 } nedner_info;
@@ -138,7 +154,8 @@ typedef struct {
   double ms_execute;       /* autotune: forward execute time of the chosen shape, ms */
 } nedner_tuning;
 
-/* Fill a descriptor with the defaults (w = 12, sigma = 2, tau_scale = 1, FP32). */
+/* Fill a descriptor with the defaults (w = 12, sigma = 2, tau_scale = 1, FP32,
+   Gaussian window). */
 void nedner_desc_init(nedner_desc* desc);
 
 /* Host-only validation of a descriptor (no HIP call). Returns NEDNER_E_ARG,

@@ -29,6 +29,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libnedner.so")
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "fp32_plain": 3}
 KINDS = {"volume": 0, "spectrum": 1, "grid": 2}
 FLAGS = {"allow_alias": 1, "wrap": 2, "deterministic": 4, "no_autotune": 8}
+WINDOWS = {"gaussian": 0, "kaiser_bessel": 1, "kb": 1}
 STATUS = {0: "ok", 1: "E_ARG", 2: "E_ALIAS", 3: "E_OOM", 4: "E_WORKSPACE", 5: "E_HIP",
           6: "E_UNSUPPORTED", 7: "E_STATE"}
 
@@ -49,7 +50,8 @@ class desc_struct(ctypes.Structure):
                 ("d1", ctypes.c_double), ("d2", ctypes.c_double), ("d3", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("w", ctypes.c_int32), ("sigma", ctypes.c_double),
                 ("tau_scale", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("rows_per_wave", ctypes.c_int32), ("time_per_lane", ctypes.c_int32)]
+                ("rows_per_wave", ctypes.c_int32), ("time_per_lane", ctypes.c_int32),
+                ("window", ctypes.c_int32)]
 
 
 class info_struct(ctypes.Structure):
@@ -135,7 +137,7 @@ def _check(st: int):
 
 def _make_desc(xy, h, nt, dt, n1, n2, n3, c=1.0, t0=0.0, a1=0.0, a2=0.0, d1=0.0, d2=0.0,
                d3=0.0, precision="fp32c", w=12, sigma=2.0, tau_scale=1.0, flags=0,
-               rows_per_wave=0, time_per_lane=0):
+               rows_per_wave=0, time_per_lane=0, window="gaussian"):
     L = lib()
     d = desc_struct()
     L.nedner_desc_init(ctypes.byref(d))
@@ -161,6 +163,7 @@ def _make_desc(xy, h, nt, dt, n1, n2, n3, c=1.0, t0=0.0, a1=0.0, a2=0.0, d1=0.0,
         flags = sum(FLAGS[f] for f in flags)
     d.flags = int(flags)
     d.rows_per_wave, d.time_per_lane = int(rows_per_wave), int(time_per_lane)
+    d.window = WINDOWS[window] if isinstance(window, str) else int(window)
     return d, keep
 
 
@@ -181,12 +184,13 @@ class Plan:
     samples `nt` at t0 + n dt, sound speed `c`, output `volume` = (N1, N2, N3)
     with voxel (i1, i2, i3) at (a1 + i1 d1, a2 + i2 d2, i3 d3); d1, d2 default
     to a unit aperture, d3 to c nt dt / N3. `precision` is one of "fp64",
-    "fp32", "fp32c" (compensated spreading) or "fp32_plain".
+    "fp32", "fp32c" (compensated spreading) or "fp32_plain"; `window` is
+    "gaussian" (default) or "kaiser_bessel" with `w` taps per axis.
     """
 
     def __init__(self, xy, nt, dt, volume, c=1.0, h=None, t0=0.0, a1=0.0, a2=0.0, d1=0.0,
                  d2=0.0, d3=0.0, precision="fp32c", w=12, sigma=2.0, tau_scale=1.0, flags=0,
-                 rows_per_wave=0, time_per_lane=0, device=None):
+                 rows_per_wave=0, time_per_lane=0, window="gaussian", device=None):
         import torch
         self._torch = torch
         if not torch.cuda.is_available():
@@ -195,10 +199,11 @@ class Plan:
         n1, n2, n3 = (int(v) for v in volume)
         d, keep = _make_desc(xy, h, nt, dt, n1, n2, n3, c=c, t0=t0, a1=a1, a2=a2, d1=d1, d2=d2,
                              d3=d3, precision=precision, w=w, sigma=sigma, tau_scale=tau_scale,
-                             flags=flags, rows_per_wave=rows_per_wave, time_per_lane=time_per_lane)
+                             flags=flags, rows_per_wave=rows_per_wave, time_per_lane=time_per_lane,
+                             window=window)
         self.m, self.nt, self.volume = int(d.m), int(nt), (n1, n2, n3)
         self.precision = precision
-        self._w, self._sigma = int(w), float(sigma)
+        self._w, self._sigma, self._window = int(w), float(sigma), int(d.window)
         self.dtype = torch.float64 if d.prec == 0 else torch.float32
         self._plan = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -308,7 +313,8 @@ class Plan:
     def cache_key(self) -> str:
         arch = self._torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
         n1, n2, n3 = self.volume
-        return f"{arch}|{self.precision}|m{self.m}|nt{self.nt}|{n1}x{n2}x{n3}|w{self._w}|s{self._sigma}"
+        return (f"{arch}|{self.precision}|m{self.m}|nt{self.nt}|{n1}x{n2}x{n3}|w{self._w}|s{self._sigma}"
+                f"|win{self._window}")
 
     def autotune(self, g=None, cache: str | None = None) -> dict:
         """Pick the fastest launch shape (sweep length, samples per lane, pass
@@ -372,7 +378,7 @@ class BatchPlan:
     """
 
     def __init__(self, problems, precision="fp32c", w=12, sigma=2.0, tau_scale=1.0, flags=0,
-                 time_per_lane=0, device=None):
+                 time_per_lane=0, window="gaussian", device=None):
         import torch
         self._torch = torch
         if not torch.cuda.is_available():
@@ -386,7 +392,7 @@ class BatchPlan:
             n1, n2, n3 = (int(v) for v in pr.pop("volume"))
             d, k = _make_desc(pr.pop("xy"), pr.pop("h", None), pr.pop("nt"), pr.pop("dt"), n1, n2, n3,
                               precision=precision, w=w, sigma=sigma, tau_scale=tau_scale, flags=flags,
-                              time_per_lane=time_per_lane, **pr)
+                              time_per_lane=time_per_lane, window=window, **pr)
             descs[i] = d
             keep.append(k)
             self.shapes.append(((int(d.m), int(d.nt)), (n1, n2, n3)))

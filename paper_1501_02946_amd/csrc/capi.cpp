@@ -79,8 +79,51 @@ struct Derived {
   long n1, n2, ntt;
   double L1, L2, D3, beta;
   int W, TT, S, nseg, nchunk, CB, K2, J1;
+  int window;
   double max_theta;
 };
+
+// Modified Bessel function I0 by its power series sum_k (x^2/4)^k / (k!)^2,
+// summed until a term no longer changes the (all positive) sum.
+double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 1000; ++k) {
+    term *= q / (double(k) * double(k));
+    const double next = sum + term;
+    if (next == sum) break;
+    sum = next;
+  }
+  return sum;
+}
+
+// The window and its Fourier transform (nedner_window), x and xi in grid units.
+double window_phi(const Derived& v, double x) {
+  if (v.window == NEDNER_WINDOW_KAISER_BESSEL) {
+    const double a = 2.0 * x / v.W;
+    return std::fabs(a) < 1.0 ? bessel_i0(v.beta * std::sqrt(1.0 - a * a)) : 0.0;
+  }
+  return std::exp(-v.beta * x * x);
+}
+
+// phihat at mode k of an n-point grid: xi = k / n
+double window_phihat(const Derived& v, double k, double n) {
+  const double xi = k / n;
+  if (v.window == NEDNER_WINDOW_KAISER_BESSEL) {
+    const double w = M_PI * v.W * xi;
+    const double z2 = v.beta * v.beta - w * w;
+    if (z2 > 0) {
+      const double z = std::sqrt(z2);
+      return v.W * std::sinh(z) / z;
+    }
+    if (z2 < 0) {
+      const double z = std::sqrt(-z2);
+      return v.W * std::sin(z) / z;
+    }
+    return double(v.W);
+  }
+  return std::sqrt(M_PI / v.beta) * std::exp(-M_PI * M_PI * xi * xi / v.beta);
+}
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -160,7 +203,18 @@ nedner_status validate_impl(const nedner_desc* d, Derived* out) {
   v.L2 = d->n2 * d->d2;
   v.D3 = d->d3 > 0 ? d->d3 : d->c * double(d->nt) * d->dt / d->n3;
   v.W = d->w;
-  v.beta = M_PI * (d->sigma - 0.5) / (d->sigma * (d->w / 2.0)) / d->tau_scale;
+  if (d->window != NEDNER_WINDOW_GAUSSIAN && d->window != NEDNER_WINDOW_KAISER_BESSEL)
+    return fail(NEDNER_E_ARG, "unknown window");
+  v.window = d->window;
+  if (v.window == NEDNER_WINDOW_KAISER_BESSEL && (d->w < 4 || d->w > 12))
+    return fail(NEDNER_E_UNSUPPORTED, "the Kaiser-Bessel window is built for 4 to 12 taps");
+  if (v.window == NEDNER_WINDOW_KAISER_BESSEL) {
+    const double r = (d->w / d->sigma) * (d->sigma - 0.5);
+    if (r * r <= 0.8) return fail(NEDNER_E_ARG, "Kaiser-Bessel window needs (w/sigma)^2 (sigma-1/2)^2 > 0.8");
+    v.beta = M_PI * std::sqrt(r * r - 0.8);
+  } else {
+    v.beta = M_PI * (d->sigma - 0.5) / (d->sigma * (d->w / 2.0)) / d->tau_scale;
+  }
   v.K2 = d->n2 / 2 + 1;
   v.J1 = d->n1 + 1;
   // positions
@@ -223,8 +277,6 @@ struct Geometry {
   std::vector<int> cellbeg;     // [n2 * nseg][CB]
 };
 
-double phi(double beta, double x) { return std::exp(-beta * x * x); }
-
 void build_geometry(const nedner_desc& d, const Derived& v, Geometry& G) {
   const int64_t M = d.m;
   const int W = v.W, h = W / 2 - 1;
@@ -262,9 +314,10 @@ void build_geometry(const nedner_desc& d, const Derived& v, Geometry& G) {
         double w;
         if (plain) {
           const float df = float(o) - float(f);
-          w = double(std::exp(-float(v.beta) * df * df));
+          w = v.window == NEDNER_WINDOW_GAUSSIAN ? double(std::exp(-float(v.beta) * df * df))
+                                                 : double(float(window_phi(v, double(df))));
         } else {
-          w = phi(v.beta, double(o) - f);
+          w = window_phi(v, double(o) - f);
         }
         if (ax == 0)
           G.w1[m * W + k] = s * w;
@@ -324,10 +377,6 @@ void build_geometry(const nedner_desc& d, const Derived& v, Geometry& G) {
       cb[Vend - Vstart + 1] = int(G.ent_m.size());
     }
   }
-}
-
-double phihat(double beta, double k, double n) {
-  return std::sqrt(M_PI / beta) * std::exp(-M_PI * M_PI * k * k / (beta * n * n));
 }
 
 struct DevAlloc {
@@ -519,6 +568,7 @@ nedner_status create_one(const nedner_desc* desc, int device, nedner_plan* out) 
   k.nchunk = v.nchunk;
   k.prec = desc->prec;
   k.beta = v.beta;
+  k.window = v.window;
   k.cdtnt = desc->c * desc->dt * double(v.ntt);
   k.inv_L1sq = 1.0 / (v.L1 * v.L1);
   k.inv_L2sq = 1.0 / (v.L2 * v.L2);
@@ -536,9 +586,9 @@ nedner_status create_one(const nedner_desc* desc, int device, nedner_plan* out) 
 
   // deconvolution and precorrection tables
   std::vector<double> d1(v.J1), d2(v.K2), dtb(desc->nt);
-  for (int je = 0; je < v.J1; ++je) d1[je] = 1.0 / phihat(v.beta, je - desc->n1 / 2, double(v.n1));
-  for (int k2 = 0; k2 < v.K2; ++k2) d2[k2] = 1.0 / phihat(v.beta, k2, double(v.n2));
-  for (int64_t n = 0; n < desc->nt; ++n) dtb[n] = 1.0 / phihat(v.beta, double(n - desc->nt / 2), double(v.ntt));
+  for (int je = 0; je < v.J1; ++je) d1[je] = 1.0 / window_phihat(v, je - desc->n1 / 2, double(v.n1));
+  for (int k2 = 0; k2 < v.K2; ++k2) d2[k2] = 1.0 / window_phihat(v, k2, double(v.n2));
+  for (int64_t n = 0; n < desc->nt; ++n) dtb[n] = 1.0 / window_phihat(v, double(n - desc->nt / 2), double(v.ntt));
 
   DevAlloc A;
   // FFT pass shape: 16 lines (whole 128-byte rows of float pairs), 512

@@ -69,6 +69,44 @@ __device__ __forceinline__ void sincos_pi<float>(float v, float* s, float* c) { 
 template <>
 __device__ __forceinline__ void sincos_pi<double>(double v, double* s, double* c) { sincospi(v, s, c); }
 
+// Modified Bessel function I0 for the Kaiser-Bessel window taps.
+// float: the polynomial approximations 9.8.1 (|y| <= 3.75) and 9.8.2 (y > 3.75,
+// for sqrt(y) exp(-y) I0(y)) of Abramowitz and Stegun, Handbook of Mathematical
+// Functions, relative error below 4e-7; double: the power series
+// sum_k (y^2/4)^k / (k!)^2, summed until a term no longer changes the sum.
+__device__ __forceinline__ float bessel_i0(float y) {
+  if (y <= 3.75f) {
+    const float t = (y * (1.0f / 3.75f)) * (y * (1.0f / 3.75f));
+    return 1.0f + t * (3.5156229f + t * (3.0899424f + t * (1.2067492f + t * (0.2659732f +
+           t * (0.0360768f + t * 0.0045813f)))));
+  }
+  const float u = 3.75f / y;
+  const float q = 0.39894228f + u * (0.01328592f + u * (0.00225319f + u * (-0.00157565f + u * (0.00916281f +
+                  u * (-0.02057706f + u * (0.02635537f + u * (-0.01647633f + u * 0.00392377f)))))));
+  return q * expf(y) * rsqrtf(y);
+}
+
+__device__ __forceinline__ double bessel_i0(double y) {
+  const double q = 0.25 * y * y;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 1000; ++k) {
+    term *= q / (double(k) * double(k));
+    const double next = sum + term;
+    if (next == sum) break;
+    sum = next;
+  }
+  return sum;
+}
+
+// Kaiser-Bessel tap at offset d (grid units): I0(beta sqrt(1 - (2d/W)^2)) for
+// |d| < W/2, else 0; twow = 2/W.
+template <typename R>
+__device__ __forceinline__ R kb_tap(R d, R beta, R twow) {
+  const R a = d * twow;
+  const R s = R(1) - a * a;
+  return s > R(0) ? bessel_i0(beta * sqrt(s)) : R(0);
+}
+
 // Frequency data of one output l of a column: grid position x = q0 + fr,
 // the weight W(j,l) times the scale, and exp(-i phase).
 template <typename R, bool ARGS64>
@@ -170,7 +208,7 @@ __device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int wav
 
 // One wavefront per column; a workgroup of CPW wavefronts shares the twiddles.
 // SPEC: write the full spectrum F (N1, N2, N3) in FFT order instead of Z1.
-template <typename R, int W, bool ARGS64, bool SPEC, int PPT>
+template <typename R, int W, bool ARGS64, bool SPEC, int PPT, bool KBW>
 __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const cpx<R>* __restrict__ G,
                                             void* out) {
   extern __shared__ __align__(16) char smem[];
@@ -217,6 +255,7 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
 #pragma unroll
   for (int k = 0; k < W / 2; ++k) rk[k] = R(exp(-p.beta * (2 * k + 1)));
   const bool chain = p.beta <= 8.0;  // exp(2 beta fr) stays far from overflow
+  const R twow = R(2.0 / W);
   // the value of output li = lane + 64 i, i < NL_REG, when they stay in registers
   cpx<R> hl[NL_REG];
   const bool in_regs = col_fl_in_regs(N3);
@@ -226,7 +265,11 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
     // taps q0 - W/2 + 1 .. q0 + W/2 read from b .. b + W - 1 (no wrap)
     const cpx<R>* Bq = B + pmodc(lp.q0 - W / 2 + 1, ntt) + (W / 2 - 1);
     cpx<R> H;
-    if (chain) {
+    if constexpr (KBW) {
+      H = cpx<R>{R(0), R(0)};
+#pragma unroll
+      for (int o = -W / 2 + 1; o <= W / 2; ++o) H = H + Bq[o] * kb_tap<R>(R(o) - lp.fr, beta, twow);
+    } else if (chain) {
       const R fr = lp.fr;
       const R up = wexp<R>(R(2) * beta * fr);
       const R dn = wexp<R>(R(-2) * beta * fr);
@@ -318,9 +361,9 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
   }
 }
 
-template <typename R, int W, bool ARGS64, bool SPEC, int PPT>
+template <typename R, int W, bool ARGS64, bool SPEC, int PPT, bool KBW>
 __global__ __launch_bounds__(512) void k_column(KP p, int ncol, const cpx<R>* __restrict__ G, void* out) {
-  column_body<R, W, ARGS64, SPEC, PPT>(p, ncol, blockIdx.x, G, out);
+  column_body<R, W, ARGS64, SPEC, PPT, KBW>(p, ncol, blockIdx.x, G, out);
 }
 
 // First index i in [lo, hi) with q[i] >= v (q non-decreasing).
@@ -335,7 +378,7 @@ __device__ __forceinline__ int lower_bound_i(const int* q, int lo, int hi, int v
   return lo;
 }
 
-template <typename R, int W, bool ARGS64, int PPT>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW>
 __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap, int bx,
                                                 const cpx<R>* __restrict__ Z1, cpx<R>* __restrict__ G) {
   extern __shared__ __align__(16) char smem[];
@@ -388,6 +431,7 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
   // non-decreasing in l, so the l covering q form a contiguous range.
   cpx<R>* Bp = sm.a;
   const R beta = R(p.beta);
+  const R twow = R(2.0 / W);
   for (int q = lane; q < ntt; q += 64) {
     const int qc = q < ntt / 2 ? q : q - ntt;
     cpx<R> acc = {R(0), R(0)};
@@ -398,7 +442,10 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
       const int hi = lower_bound_i(sm.q0, lo, N3 + 1, qv + W / 2);
       for (int li = lo; li < hi; ++li) {
         const R d = R(qv - sm.q0[li]) - sm.fr[li];
-        acc = acc + sm.fl[li] * wexp<R>(-beta * d * d);
+        if constexpr (KBW)
+          acc = acc + sm.fl[li] * kb_tap<R>(d, beta, twow);
+        else
+          acc = acc + sm.fl[li] * wexp<R>(-beta * d * d);
       }
     }
     Bp[q] = acc;
@@ -412,10 +459,10 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
   }
 }
 
-template <typename R, int W, bool ARGS64, int PPT>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW>
 __global__ __launch_bounds__(512) void k_column_adj(KP p, int ncol, int mwrap, const cpx<R>* __restrict__ Z1,
                                                     cpx<R>* __restrict__ G) {
-  column_adj_body<R, W, ARGS64, PPT>(p, ncol, mwrap, blockIdx.x, Z1, G);
+  column_adj_body<R, W, ARGS64, PPT, KBW>(p, ncol, mwrap, blockIdx.x, Z1, G);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -447,24 +494,24 @@ static int column_ppt(const KP& p) {
   return need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
 }
 
-template <typename R, int W, bool ARGS64, int PPT>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW>
 static hipError_t column_wp(const KP& p, const void* G, void* out, int spec, hipStream_t s) {
   const int cpw = cols_per_wg<R>(p, false);
   const int ncol = p.J1 * p.K2;
   const size_t sh = col_shared_bytes<R>(p.ntt, p.N3) + cpw * col_wave_bytes<R>(p.ntt, p.N3, false);
   dim3 grid((ncol + cpw - 1) / cpw);
-  hipError_t e = allow_smem(spec ? k_column<R, W, ARGS64, true, PPT> : k_column<R, W, ARGS64, false, PPT>, sh);
+  hipError_t e = allow_smem(spec ? k_column<R, W, ARGS64, true, PPT, KBW> : k_column<R, W, ARGS64, false, PPT, KBW>, sh);
   if (e != hipSuccess) return e;
   if (spec)
-    hipLaunchKernelGGL((k_column<R, W, ARGS64, true, PPT>), grid, dim3(64 * cpw), sh, s, p, ncol,
+    hipLaunchKernelGGL((k_column<R, W, ARGS64, true, PPT, KBW>), grid, dim3(64 * cpw), sh, s, p, ncol,
                        static_cast<const cpx<R>*>(G), out);
   else
-    hipLaunchKernelGGL((k_column<R, W, ARGS64, false, PPT>), grid, dim3(64 * cpw), sh, s, p, ncol,
+    hipLaunchKernelGGL((k_column<R, W, ARGS64, false, PPT, KBW>), grid, dim3(64 * cpw), sh, s, p, ncol,
                        static_cast<const cpx<R>*>(G), out);
   return hipGetLastError();
 }
 
-template <typename R, int W, bool ARGS64, int PPT>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW>
 static hipError_t column_adj_wp(const KP& p, const void* Z1, void* G, hipStream_t s) {
   const int cpw = cols_per_wg<R>(p, true);
   const int ncol = p.J1 * p.K2;
@@ -475,41 +522,51 @@ static hipError_t column_adj_wp(const KP& p, const void* Z1, void* G, hipStream_
                                      (p.N2 / 2.0) * (p.N2 / 2.0) * p.inv_L2sq +
                                      (p.N3 / 2.0) * (p.N3 / 2.0) * p.bz);
   const int mwrap = 1 + int((xmax + W) / p.ntt);
-  hipError_t e = allow_smem(k_column_adj<R, W, ARGS64, PPT>, sh);
+  hipError_t e = allow_smem(k_column_adj<R, W, ARGS64, PPT, KBW>, sh);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_column_adj<R, W, ARGS64, PPT>), grid, dim3(64 * cpw), sh, s, p, ncol, mwrap,
+  hipLaunchKernelGGL((k_column_adj<R, W, ARGS64, PPT, KBW>), grid, dim3(64 * cpw), sh, s, p, ncol, mwrap,
                      static_cast<const cpx<R>*>(Z1), static_cast<cpx<R>*>(G));
   return hipGetLastError();
 }
 
-template <typename R, int W, bool ARGS64>
+template <typename R, int W, bool ARGS64, bool KBW>
 static hipError_t column_w(const KP& p, const void* G, void* out, int spec, hipStream_t s) {
   switch (column_ppt(p)) {
-    case 4: return column_wp<R, W, ARGS64, 4>(p, G, out, spec, s);
-    case 8: return column_wp<R, W, ARGS64, 8>(p, G, out, spec, s);
-    case 16: return column_wp<R, W, ARGS64, 16>(p, G, out, spec, s);
-    case 32: return column_wp<R, W, ARGS64, 32>(p, G, out, spec, s);
-    default: return column_wp<R, W, ARGS64, 64>(p, G, out, spec, s);
+    case 4: return column_wp<R, W, ARGS64, 4, KBW>(p, G, out, spec, s);
+    case 8: return column_wp<R, W, ARGS64, 8, KBW>(p, G, out, spec, s);
+    case 16: return column_wp<R, W, ARGS64, 16, KBW>(p, G, out, spec, s);
+    case 32: return column_wp<R, W, ARGS64, 32, KBW>(p, G, out, spec, s);
+    default: return column_wp<R, W, ARGS64, 64, KBW>(p, G, out, spec, s);
   }
 }
 
-template <typename R, int W, bool ARGS64>
+template <typename R, int W, bool ARGS64, bool KBW>
 static hipError_t column_adj_w(const KP& p, const void* Z1, void* G, hipStream_t s) {
   switch (column_ppt(p)) {
-    case 4: return column_adj_wp<R, W, ARGS64, 4>(p, Z1, G, s);
-    case 8: return column_adj_wp<R, W, ARGS64, 8>(p, Z1, G, s);
-    case 16: return column_adj_wp<R, W, ARGS64, 16>(p, Z1, G, s);
-    case 32: return column_adj_wp<R, W, ARGS64, 32>(p, Z1, G, s);
-    default: return column_adj_wp<R, W, ARGS64, 64>(p, Z1, G, s);
+    case 4: return column_adj_wp<R, W, ARGS64, 4, KBW>(p, Z1, G, s);
+    case 8: return column_adj_wp<R, W, ARGS64, 8, KBW>(p, Z1, G, s);
+    case 16: return column_adj_wp<R, W, ARGS64, 16, KBW>(p, Z1, G, s);
+    case 32: return column_adj_wp<R, W, ARGS64, 32, KBW>(p, Z1, G, s);
+    default: return column_adj_wp<R, W, ARGS64, 64, KBW>(p, Z1, G, s);
   }
 }
+
+// The Kaiser-Bessel window is instantiated for the tap counts it is meant
+// for (4 to 12); the descriptor check rejects the others.
+constexpr bool kb_width(int W) { return W >= 4 && W <= 12; }
 
 template <typename R, bool ARGS64>
 hipError_t column_a(const KP& p, const void* in, void* out, int spec, hipStream_t s, bool adj) {
   switch (p.W) {
-#define NEDNER_CW(WV) \
-  case WV:            \
-    return adj ? column_adj_w<R, WV, ARGS64>(p, in, out, s) : column_w<R, WV, ARGS64>(p, in, out, spec, s);
+#define NEDNER_CW(WV)                                                                                   \
+  case WV:                                                                                             \
+    if constexpr (kb_width(WV)) {                                                                      \
+      if (p.window == 1)                                                                               \
+        return adj ? column_adj_w<R, WV, ARGS64, true>(p, in, out, s)                                  \
+                   : column_w<R, WV, ARGS64, true>(p, in, out, spec, s);                               \
+    }                                                                                                  \
+    if (p.window != 0) return hipErrorInvalidValue;                                                    \
+    return adj ? column_adj_w<R, WV, ARGS64, false>(p, in, out, s) : column_w<R, WV, ARGS64, false>(p, in, out, spec, s);
     NEDNER_CW(2)
     NEDNER_CW(4)
     NEDNER_CW(6)
@@ -525,19 +582,19 @@ hipError_t column_a(const KP& p, const void* in, void* out, int spec, hipStream_
 }
 
 // ---------------------------------------------------------------- batched
-template <typename R, int W, bool ARGS64, int PPT>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW>
 __global__ __launch_bounds__(512) void k_column_many(const BatchProb* __restrict__ bp, WorkList wl) {
   work_loop(wl, [&](int prob, int local) {
     const BatchProb& B = bp[prob];
     const KP& p = B.kp;
-    column_body<R, W, ARGS64, false, PPT>(p, p.J1 * p.K2, local, static_cast<const cpx<R>*>(B.b0), B.b1);
+    column_body<R, W, ARGS64, false, PPT, KBW>(p, p.J1 * p.K2, local, static_cast<const cpx<R>*>(B.b0), B.b1);
   });
 }
 
-template <typename R, int W, bool ARGS64, int PPT>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW>
 static hipError_t column_many_wp(const BatchProb* bp, const WorkList& wl, int cpw, size_t smem, hipStream_t s) {
   if (wl.total <= 0) return hipSuccess;
-  auto k = k_column_many<R, W, ARGS64, PPT>;
+  auto k = k_column_many<R, W, ARGS64, PPT, KBW>;
   hipError_t e = allow_smem(k, smem);
   if (e != hipSuccess) return e;
   int per_cu = 0, dev = 0, cus = 256;
@@ -554,15 +611,21 @@ static hipError_t column_many_wp(const BatchProb* bp, const WorkList& wl, int cp
 template <typename R, bool ARGS64>
 hipError_t column_many_a(const KP& p0, int ppt, const BatchProb* bp, const WorkList& wl, int cpw,
                                 size_t smem, hipStream_t s) {
+#define NEDNER_CMPK(WV, KB)                                                              \
+    switch (ppt) {                                                                       \
+      case 4: return column_many_wp<R, WV, ARGS64, 4, KB>(bp, wl, cpw, smem, s);         \
+      case 8: return column_many_wp<R, WV, ARGS64, 8, KB>(bp, wl, cpw, smem, s);         \
+      case 16: return column_many_wp<R, WV, ARGS64, 16, KB>(bp, wl, cpw, smem, s);       \
+      case 32: return column_many_wp<R, WV, ARGS64, 32, KB>(bp, wl, cpw, smem, s);       \
+      default: return column_many_wp<R, WV, ARGS64, 64, KB>(bp, wl, cpw, smem, s);       \
+    }
 #define NEDNER_CMP(WV)                                                                   \
   case WV:                                                                               \
-    switch (ppt) {                                                                       \
-      case 4: return column_many_wp<R, WV, ARGS64, 4>(bp, wl, cpw, smem, s);             \
-      case 8: return column_many_wp<R, WV, ARGS64, 8>(bp, wl, cpw, smem, s);             \
-      case 16: return column_many_wp<R, WV, ARGS64, 16>(bp, wl, cpw, smem, s);           \
-      case 32: return column_many_wp<R, WV, ARGS64, 32>(bp, wl, cpw, smem, s);           \
-      default: return column_many_wp<R, WV, ARGS64, 64>(bp, wl, cpw, smem, s);           \
-    }
+    if constexpr (kb_width(WV)) {                                                        \
+      if (p0.window == 1) { NEDNER_CMPK(WV, true) }                                      \
+    }                                                                                    \
+    if (p0.window != 0) return hipErrorInvalidValue;                                     \
+    NEDNER_CMPK(WV, false)
   switch (p0.W) {
     NEDNER_CMP(2)
     NEDNER_CMP(4)
@@ -575,6 +638,7 @@ hipError_t column_many_a(const KP& p0, int ppt, const BatchProb* bp, const WorkL
     default: return hipErrorInvalidValue;
   }
 #undef NEDNER_CMP
+#undef NEDNER_CMPK
 }
 
 }  // namespace nedner

@@ -223,7 +223,8 @@ __device__ __forceinline__ void spread_body(const KP& p, int bx, const int* __re
   }
 }
 
-// Staged variant. Samples are staged in batches of BE entries: while the wave accumulates the
+// Staged variant. Samples are staged in batches of BE = 4 entries: while the
+// wave accumulates the
 // entries of one batch, whose samples sit in this lane's LDS slots, the samples
 // of the next batch are in flight into registers; at the batch boundary they
 // go to LDS and the loads of the batch after are issued. A wave thus waits on
@@ -234,7 +235,7 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
                                                    const int* __restrict__ em, const WT* __restrict__ ew,
                                                    const WT* __restrict__ w1t, const R* __restrict__ g,
                                                    R* __restrict__ U) {
-  constexpr int BE = sizeof(R) == 4 ? 4 : 2;
+  constexpr int BE = 4;
   __shared__ R stage[4][BE * 64 * TT];
   const int lane = threadIdx.x & 63;
   R* __restrict__ stg = stage[threadIdx.x >> 6] + lane * TT;
@@ -256,7 +257,9 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
   const int Nt = p.Nt;
   const int tb = chunk * 64 * TT + lane * TT;
   const bool lane_ok = tb < Nt;
-  const int toff = lane_ok ? tb : 0;
+  // unsigned lane offset: a uniform row address plus a 32-bit lane offset
+  // lets the loads take their base from scalar registers
+  const unsigned toff = lane_ok ? unsigned(tb) : 0u;
 
   A acc[W][TT];
 #pragma unroll
@@ -274,7 +277,10 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
   auto issue = [&](int e0) {
     if (e0 < eall) {
 #pragma unroll
-      for (int j = 0; j < BE; ++j) load_tt<TT>(nx[j], g + (size_t)mp[j] * Nt + toff, TT, VEC);
+      for (int j = 0; j < BE; ++j) {
+        const R* __restrict__ row = g + (size_t)mp[j] * Nt;
+        load_tt<TT>(nx[j], row + toff, TT, VEC);
+      }
     }
 #pragma unroll
     for (int j = 0; j < BE; ++j) mp[j] = em[e0 + BE + j];
@@ -311,27 +317,29 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
           issue(nb);
         }
         const int j = e - (nb - BE);
-        A gd[TT];
+        R gv[TT];
 #pragma unroll
-        for (int t = 0; t < TT; ++t) gd[t] = A(stg[j * 64 * TT + t]);
+        for (int t = 0; t < TT; ++t) gv[t] = stg[j * 64 * TT + t];
         WT wc[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) wc[k] = wn[k];
         const WT w2c = w2n;
-        // keep the next entry's loads behind the wait for this entry's data:
-        // a scalar load issued before it would be waited for as well
+        // wait for this entry's samples and weights here, and keep the next
+        // entry's scalar loads behind that wait: a scalar load issued before it
+        // would be waited for as well (lgkmcnt(0); vmcnt and expcnt untouched)
+        __builtin_amdgcn_s_waitcnt(0xC07F);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int k = 0; k < W; ++k) wn[k] = w1t[(size_t)mn * W + k];
         w2n = ew[e + 1];
         mn = em[e + 2];
+        // one time sample at a time: two registers for the scaled sample
+        // instead of 2 TT keep the kernel within four wavefronts per SIMD
 #pragma unroll
-        for (int t = 0; t < TT; ++t) gd[t] *= A(w2c);
+        for (int t = 0; t < TT; ++t) {
+          const A gt = A(gv[t]) * A(w2c);
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
-          const A w = A(wc[k]);
-#pragma unroll
-          for (int t = 0; t < TT; ++t) acc[(r + k + W / 2 + 1) % W][t] += w * gd[t];
+          for (int k = 0; k < W; ++k) acc[(r + k + W / 2 + 1) % W][t] += A(wc[k]) * gt;
         }
         ++e;
       }

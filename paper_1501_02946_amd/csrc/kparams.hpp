@@ -34,9 +34,10 @@ struct KP {
   int pass_lines; // FFT passes: lines per workgroup (power of two, upper bound)
   int pass_threads; // FFT passes: threads per workgroup (multiple of 64, <= 512)
   int pass_ip;    // FFT passes: in-place (1) or ping-pong (0) transform
+  int window;     // 0: Gaussian exp(-beta x^2); 1: Kaiser-Bessel I0(beta sqrt(1 - (2x/W)^2))
 
   // ---- window and frequency constants (double, reduced on the host) -----
-  double beta;      // phi(x) = exp(-beta x^2), x in grid units, all three axes
+  double beta;      // window parameter (see window), x in grid units, all three axes
   double cdtnt;     // c * dt * ntt: x(j,l) = sign(l) cdtnt |K|/(2 pi)
   double inv_L1sq;  // 1 / L1^2
   double inv_L2sq;  // 1 / L2^2

@@ -44,3 +44,17 @@ def small_problem(seed=0, s=12, nt=40, n=(12, 12, 20), jitter=0.4, c=1.0, t0=0.0
 
 def phihat(beta, k, n):
     return math.sqrt(math.pi / beta) * np.exp(-math.pi ** 2 * np.asarray(k, float) ** 2 / (beta * n * n))
+
+
+def beta_kb(w, sigma=2.0):
+    """Kaiser-Bessel shape parameter for w taps at oversampling sigma (Beatty et al. 2005)."""
+    return math.pi * math.sqrt((w / sigma) ** 2 * (sigma - 0.5) ** 2 - 0.8)
+
+
+def phihat_kb(beta, w, k, n):
+    """Fourier transform of I0(beta sqrt(1 - (2x/w)^2)) on |x| < w/2 at xi = k/n."""
+    z2 = beta ** 2 - (math.pi * w * np.asarray(k, float) / n) ** 2
+    z = np.sqrt(np.abs(z2))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        v = np.where(z2 > 0, np.sinh(z) / z, np.where(z2 < 0, np.sin(z) / z, 1.0))
+    return w * v

@@ -89,6 +89,9 @@ def test_valid_descriptor():
     (dict(time_per_lane=3), E_ARG),
     (dict(h=np.array([1.0, -0.5])), E_ARG),
     (dict(d3=-1.0), E_ARG),
+    (dict(window=2), E_ARG),                                   # unknown window
+    (dict(window="kaiser_bessel", w=14), E_UNSUPPORTED),       # KB built for 4..12 taps
+    (dict(window="kaiser_bessel", w=2), E_UNSUPPORTED),
     (dict(n1=14), E_UNSUPPORTED),                              # 28 is not 5-smooth
     (dict(nt=14 * 8), E_UNSUPPORTED),
     (dict(nt=16, dt=1 / 16, n3=32), E_ALIAS),                  # |omega| dt >= pi
