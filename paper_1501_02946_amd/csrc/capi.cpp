@@ -519,10 +519,51 @@ nedner_status hip_fail(nedner_plan p, hipError_t e, const char* where) {
   return fail(NEDNER_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-nedner_status create_one(const nedner_desc* desc, int device, nedner_plan* out) {
+// Sweep length when the descriptor leaves it open: the number of segments
+// whose spreading launch makes the fewest rounds of resident workgroups times
+// rows per sweep (each wave sweeps S + W - 1 cell rows), S in [2W, 256].
+// A launch whose last round is nearly empty runs its tail at a fraction of the
+// chip, so whole rounds of long sweeps beat many short ones.
+int balanced_rows(const Derived& v, long resident) {
+  const long base = (v.n2 + 3) / 4 * (long)v.nchunk;
+  int best_s = v.S;
+  double best = 1e300;
+  for (long nseg = 1; nseg <= v.n1; ++nseg) {
+    const long S = (v.n1 + nseg - 1) / nseg;
+    if (S > 256) continue;
+    if (S < 2 * v.W) break;
+    const long rounds = (base * nseg + resident - 1) / resident;
+    const double cost = double(rounds) * double(S + v.W - 1);
+    if (cost < best) {
+      best = cost;
+      best_s = int(S);
+    }
+  }
+  return best_s;
+}
+
+nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* out) {
   Derived v;
-  nedner_status st = validate_impl(desc, &v);
+  nedner_status st = validate_impl(desc_in, &v);
   if (st != NEDNER_OK) return st;
+  nedner_desc dd = *desc_in;
+  if (dd.rows_per_wave == 0) {
+    DeviceGuard g0(device);
+    int cus = 0;
+    if (g0.ok() && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        cus > 0) {
+      KP q{};
+      q.prec = dd.prec;
+      q.W = v.W;
+      q.TT = v.TT;
+      q.spread_pd = spread_opt().pd;
+      q.wide_w = dd.prec == NEDNER_FP32_COMPENSATED && spread_opt().wide;
+      dd.rows_per_wave = balanced_rows(v, long(nedner::spread_blocks_per_cu(q)) * cus);
+      st = validate_impl(&dd, &v);
+      if (st != NEDNER_OK) return st;
+    }
+  }
+  const nedner_desc* desc = &dd;
   nedner_plan p = new (std::nothrow) nedner_plan_s();
   if (!p) return fail(NEDNER_E_OOM, "host allocation failed");
   p->desc = *desc;
@@ -1074,9 +1115,13 @@ nedner_status tune_spread(nedner_plan p, const void* d_g, void* U, hipStream_t s
   else
     for (int tt : {4, 2, 1})
       if (Nt % tt == 0 && (tt == 1 || Nt >= 32 * tt)) tts.push_back(tt);
+  // sweep lengths that split the n1 rows into nseg equal segments
   std::vector<int> ss;
-  for (int S : {24, 32, 48, 64, 96})
-    if (S <= n1 && S >= W) ss.push_back(S);
+  for (int nseg = 1; nseg <= n1; ++nseg) {
+    const int S = (n1 + nseg - 1) / nseg;
+    if (S < 2 * W) break;
+    if (S <= 256 && (ss.empty() || ss.back() != S)) ss.push_back(S);
+  }
   if (ss.empty()) ss.push_back(n1);
   int bS = p->kp.S, bT = p->kp.TT, bP = p->kp.spread_pd;
   double best = 1e300;
@@ -1140,32 +1185,96 @@ nedner_status autotune_single(nedner_plan p, const void* d_g, hipStream_t s, ned
   return NEDNER_OK;
 }
 
+// Batched spreading shape: one sweep length for every problem (clamped to its
+// grid) and one sweep variant, chosen by timing the whole batch's spreading
+// launch on zero data. Problems share the chip in the batch, so the shape that
+// is fastest for a problem alone (short sweeps, to fill the chip) is not the
+// one that is fastest for the batch (long sweeps, less overlap work).
 nedner_status autotune_batch(nedner_plan bp, hipStream_t s, nedner_tuning* out) {
   if (!bp->ws || bp->ws_bytes < bp->need_ws) return fail(NEDNER_E_WORKSPACE, "autotune needs the workspace");
-  double total = 0;
-  for (size_t i = 0; i < bp->subs.size(); ++i) {
+  const int count = int(bp->subs.size());
+  // each problem's data: zeros in the second buffer of its workspace slice
+  // (the cost does not depend on the values); its first buffer takes the grid
+  std::vector<const void*> gz(count);
+  std::vector<void*> oz(count);
+  for (int i = 0; i < count; ++i) {
     nedner_plan sp = bp->subs[i];
     char* slice = static_cast<char*>(bp->ws) + bp->sub_off[i];
-    // the problem's data is not at hand: time the spreading on zeros in the
-    // second buffer of its slice (the cost does not depend on the values)
     const size_t gbytes = (size_t)sp->kp.M * sp->kp.Nt * (sp->kp.prec == NEDNER_FP64 ? 8 : 4);
-    char* gz = slice + sp->off1;
     if (gbytes > sp->need_ws - sp->off1) return fail(NEDNER_E_UNSUPPORTED, "problem data larger than its buffer");
-    if (hipMemsetAsync(gz, 0, gbytes, s) != hipSuccess) return fail(NEDNER_E_HIP, "hipMemsetAsync failed");
-    double ms = 0;
-    nedner_status st = tune_spread(sp, gz, slice, s, bp->kp0.TT, &ms);
-    if (st != NEDNER_OK) return st;
-    total += ms;
+    if (hipMemsetAsync(slice + sp->off1, 0, gbytes, s) != hipSuccess)
+      return fail(NEDNER_E_HIP, "hipMemsetAsync failed");
+    gz[i] = slice + sp->off1;
+    oz[i] = slice;
   }
-  bp->kp0.spread_pd = bp->subs[0]->kp.spread_pd;
-  for (auto* sp : bp->subs) sp->kp.spread_pd = bp->kp0.spread_pd;
-  nedner_status st = batch_build_lists(bp);
+  auto prepare = [&]() -> hipError_t {
+    for (int first = 0; first < count; first += 64) {
+      nedner::PtrChunk ch{};
+      ch.first = first;
+      ch.n = std::min(64, count - first);
+      for (int i = 0; i < ch.n; ++i) {
+        ch.g[i] = gz[first + i];
+        ch.out[i] = oz[first + i];
+      }
+      hipError_t e = nedner::launch_batch_prepare(bp->d_bp, ch, bp->d_counters, first == 0 ? nedner::ST_COUNT : 0, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  auto shape = [&](int S, int pd) -> nedner_status {
+    for (auto* sp : bp->subs) {
+      nedner_status st = set_spread_shape(sp, std::min<int>(S, sp->kp.n1), bp->kp0.TT, pd);
+      if (st != NEDNER_OK) return st;
+    }
+    bp->kp0.spread_pd = pd;
+    nedner_status st = batch_build_lists(bp);
+    if (st != NEDNER_OK) return st;
+    return batch_upload_table(bp);
+  };
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return fail(NEDNER_E_HIP, "hipEventCreate failed");
+  }
+  double best = 1e300;
+  int bS = 64, bP = 1;
+  nedner_status st = NEDNER_OK;
+  for (int pd : {1, 2}) {
+    for (int S : {32, 64, 128, 256}) {
+      st = shape(S, pd);
+      if (st != NEDNER_OK) break;
+      const auto wl = nedner::WorkList{bp->d_items + bp->stage_off[nedner::ST_SPREAD],
+                                       bp->stage_total[nedner::ST_SPREAD], bp->d_counters + nedner::ST_SPREAD};
+      double ms = 0;
+      for (int rep = 0; rep < 3 && st == NEDNER_OK; ++rep) {
+        hipError_t e = prepare();
+        if (e == hipSuccess) e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = nedner::launch_spread_many(bp->kp0, bp->d_bp, wl, 1, s);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+        if (e != hipSuccess) st = hip_fail(bp, e, "batched autotune");
+        if (rep > 0) ms += t / 2.0;  // the first launch warms up
+      }
+      if (st != NEDNER_OK) break;
+      if (ms < best) {
+        best = ms;
+        bS = S;
+        bP = pd;
+      }
+    }
+    if (st != NEDNER_OK) break;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   if (st != NEDNER_OK) return st;
-  st = batch_upload_table(bp);
+  st = shape(bS, bP);
   if (st != NEDNER_OK) return st;
   if (out) {
     get_tuning(bp->subs[0], out);
-    out->ms_spread = total;
+    out->rows_per_wave = bS;
+    out->ms_spread = best;
     out->ms_execute = 0;
   }
   return NEDNER_OK;

@@ -598,6 +598,51 @@ hipError_t launch_spread_many(const KP& p0, const BatchProb* bp, const WorkList&
   }
 }
 
+// ---------------------------------------------------------------------------
+// occupancy of the forward spreading instance a plan launches (aligned data)
+
+template <typename R, typename WT, typename A, int W, int TT>
+static int occ_wt(const KP& p) {
+  auto k = p.spread_pd == 2 ? k_spread<W, TT, R, WT, A, true, 2> : k_spread<W, TT, R, WT, A, true, 1>;
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(k), 256, 0) != hipSuccess)
+    return 1;
+  return b > 0 ? b : 1;
+}
+
+template <typename R, typename WT, typename A, int W>
+static int occ_w(const KP& p) {
+  switch (p.TT) {
+    case 1: return occ_wt<R, WT, A, W, 1>(p);
+    case 2: return occ_wt<R, WT, A, W, 2>(p);
+    case 4: return occ_wt<R, WT, A, W, 4>(p);
+    default: return 1;
+  }
+}
+
+template <typename R, typename WT, typename A>
+static int occ_p(const KP& p) {
+  switch (p.W) {
+    case 2: return occ_w<R, WT, A, 2>(p);
+    case 4: return occ_w<R, WT, A, 4>(p);
+    case 6: return occ_w<R, WT, A, 6>(p);
+    case 8: return occ_w<R, WT, A, 8>(p);
+    case 10: return occ_w<R, WT, A, 10>(p);
+    case 12: return occ_w<R, WT, A, 12>(p);
+    case 14: return occ_w<R, WT, A, 14>(p);
+    case 16: return occ_w<R, WT, A, 16>(p);
+    default: return 1;
+  }
+}
+
+int spread_blocks_per_cu(const KP& p) {
+  switch (p.prec) {
+    case PREC_FP64: return occ_p<double, double, double>(p);
+    case PREC_FP32C: return p.wide_w ? occ_p<float, double, double>(p) : occ_p<float, float, double>(p);
+    default: return occ_p<float, float, float>(p);
+  }
+}
+
 hipError_t launch_spread(const KP& p, const void* g, void* U, hipStream_t s) {
   return dispatch(p, g, U, s, false);
 }

@@ -101,6 +101,8 @@ inline hipError_t allow_smem(F kernel, size_t bytes) {
 // Host launchers (defined in the .hip files). All enqueue on `s` and return
 // the launch status.
 hipError_t launch_spread(const KP& p, const void* g, void* U, hipStream_t s);
+// Workgroups of the forward spreading kernel (prec, W, TT, spread_pd, wide_w of p) per CU.
+int spread_blocks_per_cu(const KP& p);
 hipError_t launch_gather(const KP& p, const void* U, void* g, hipStream_t s);
 hipError_t launch_lat_a(const KP& p, const void* U, void* V, hipStream_t s);
 hipError_t launch_lat_b(const KP& p, const void* V, void* G, hipStream_t s);
