@@ -38,20 +38,26 @@ WORKLOADS = {
     "c3": "65536 sensors 4x denser near the centre, 1024 samples, 30 balls + 5 bead chains -> 256x256x512",
     "c5": "192x192 sensors jittered +/-0.4 pitch, 768 samples, 20 balls + 1% noise -> 192x192x384",
     "c1": "32x32 sensors jittered +/-0.4 pitch, 128 samples, one ball -> 32x32x64",
+    "c6": "equi-steradian mask: ~1600 sensors on a 240x240 grid, h ~ r^3, 512 samples, 10 balls "
+          "+ 1% noise -> 240x240x256",
+    "c7": "128x128 sensors on the output grid nodes (equispaced, NER-only path), 512 samples, "
+          "10 balls + 1% noise -> 128x128x256",
     "c4": "64 problems, M ~ U[1024,16384] jittered, Nt in {256,512,1024}, 1-10 balls, s x s x Nt/2, "
           "one persistent launch per stage",
 }
 
 
-def stage_model(p, info, prec):
-    """Algorithmic bytes and flops of each forward stage (one launch each)."""
+def stage_model(p, info, prec, equi=False):
+    """Algorithmic bytes and flops of each forward stage (one launch each).
+    On the equispaced path the spreading is a placement: one product per sample."""
     rs = 8 if prec == "fp64" else 4
     cs = 2 * rs
     M, Nt, N1, N2, N3 = p.m, p.nt, p.n1, p.n2, p.n3
     n1, n2, ntt = info["n1_os"], info["n2_os"], info["nt_os"]
     K2, J1, W = N2 // 2 + 1, N1 + 1, 12
     return {
-        "spread": dict(bytes=rs * M * Nt + rs * n1 * n2 * Nt, flops=2 * W * W * M * Nt),
+        "spread": dict(bytes=rs * M * Nt + rs * n1 * n2 * Nt,
+                       flops=M * Nt if equi else 2 * W * W * M * Nt),
         "lat_a": dict(bytes=rs * n1 * n2 * Nt + cs * n1 * K2 * Nt,
                       flops=int(2.5 * n1 * n2 * Nt * math.log2(n2))),
         "lat_b": dict(bytes=cs * n1 * K2 * Nt + cs * K2 * J1 * Nt,
@@ -304,8 +310,10 @@ def main(argv=None):
         print(json.dumps(bench_batch(a, torch, N, synth)), flush=True)
         return 0
     p = synth.config(a.workload)
+    equi = a.workload == "c7"
+    flags = ["equispaced"] if equi else []
     plan = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0,
-                  precision=a.precision)
+                  precision=a.precision, flags=flags)
     g = torch.as_tensor(p.g, dtype=plan.dtype, device=plan.device).contiguous()
     out = torch.empty((p.n1, p.n2, p.n3), dtype=plan.dtype, device=plan.device)
 
@@ -315,7 +323,7 @@ def main(argv=None):
     points = p.m * p.nt
     value = points / (ms / 1e3) / 1e6
 
-    model = stage_model(p, plan.info, a.precision)
+    model = stage_model(p, plan.info, a.precision, equi)
     stage_rep = {}
     for name, t in stages.items():
         m = model.get(name, {})
@@ -324,7 +332,7 @@ def main(argv=None):
                                hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
     dom = max(stages, key=stages.get)
     tdom = stages[dom] / 1e3
-    if dom == "spread":
+    if dom == "spread" and not equi:
         # the spread is a W*W-tap multiply-add per (sensor, sample): ALU bound;
         # the compensated and FP64 paths accumulate with FP64 FMAs
         peak = FP64_VECTOR_TFLOPS if a.precision in ("fp32c", "fp64") else FP32_VECTOR_TFLOPS
@@ -354,7 +362,8 @@ def main(argv=None):
         "stages": stage_rep,
     }
     if not a.no_fp64 and a.precision != "fp64":
-        p64 = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0, precision="fp64")
+        p64 = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0, precision="fp64",
+                     flags=flags)
         g64 = torch.as_tensor(p.g, dtype=torch.float64, device=plan.device).contiguous()
         o64 = torch.empty((p.n1, p.n2, p.n3), dtype=torch.float64, device=plan.device)
         ms64, _ = time_steps(torch, p64, g64, o64, a.steps, a.warmup)
@@ -368,7 +377,7 @@ def main(argv=None):
     if not a.no_kb:
         # the paper's window choice: Kaiser-Bessel, 8 taps per axis instead of 12
         pkb = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0,
-                     precision=a.precision, w=8, window="kaiser_bessel")
+                     precision=a.precision, w=8, window="kaiser_bessel", flags=flags)
         okb = torch.empty((p.n1, p.n2, p.n3), dtype=plan.dtype, device=plan.device)
         mskb, _ = time_steps(torch, pkb, g, okb, a.steps, a.warmup)
         _, stkb = time_steps(torch, pkb, g, okb, a.steps, 1, profile=True)

@@ -103,6 +103,13 @@ typedef enum {
 #define NEDNER_WRAP_POSITIONS 2u   /* wrap positions into the periodic aperture */
 #define NEDNER_DETERMINISTIC 4u    /* accepted; every path is bitwise deterministic */
 #define NEDNER_NO_AUTOTUNE 8u      /* keep the built-in launch shapes */
+/* Sensors on the output grid (the NER-NUFFT case, Sec. 3 eq. (4)): every
+   position is a voxel node a + i d (i integer in [0, n)), at most one sensor
+   per node. The lateral sums of eq. (5) are then a plain DFT of the
+   zero-filled node grid: no spreading, no lateral window or oversampling,
+   only the time axis keeps the window. Positions off the grid are
+   NEDNER_E_ARG; batched plans reject the flag (NEDNER_E_UNSUPPORTED). */
+#define NEDNER_EQUISPACED 16u
 
 /* Plan descriptor. Fill with nedner_desc_init, then set the fields. */
 typedef struct {

@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libnedner.so")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "fp32_plain": 3}
 KINDS = {"volume": 0, "spectrum": 1, "grid": 2}
-FLAGS = {"allow_alias": 1, "wrap": 2, "deterministic": 4, "no_autotune": 8}
+FLAGS = {"allow_alias": 1, "wrap": 2, "deterministic": 4, "no_autotune": 8, "equispaced": 16}
 WINDOWS = {"gaussian": 0, "kaiser_bessel": 1, "kb": 1}
 STATUS = {0: "ok", 1: "E_ARG", 2: "E_ALIAS", 3: "E_OOM", 4: "E_WORKSPACE", 5: "E_HIP",
           6: "E_UNSUPPORTED", 7: "E_STATE"}

@@ -80,6 +80,7 @@ struct Derived {
   double L1, L2, D3, beta;
   int W, TT, S, nseg, nchunk, CB, K2, J1;
   int window;
+  bool equi;  // sensors on the output grid: no lateral spreading or oversampling
   double max_theta;
 };
 
@@ -172,6 +173,22 @@ size_t column_lds(const nedner_desc& d, const Derived& v) {
   return cs * (v.ntt + d.n3) + wave;
 }
 
+// Node (i1, i2) of sensor m when it sits on the output grid a + i d (after
+// wrapping into the aperture): |u - round(u)| <= 1e-9 with u = (y - a)/d.
+bool grid_node(const nedner_desc& d, const Derived& v, int64_t m, long* i) {
+  const double L[2] = {v.L1, v.L2}, a[2] = {d.a1, d.a2}, st[2] = {d.d1, d.d2};
+  const long n[2] = {d.n1, d.n2};
+  for (int ax = 0; ax < 2; ++ax) {
+    double y = d.xy[2 * m + ax] - a[ax];
+    y -= L[ax] * std::floor(y / L[ax]);
+    const double u = y / st[ax];
+    const double r = std::nearbyint(u);
+    if (std::fabs(u - r) > 1e-9) return false;
+    i[ax] = long(r) % n[ax];
+  }
+  return true;
+}
+
 nedner_status validate_impl(const nedner_desc* d, Derived* out) {
   if (!d) return fail(NEDNER_E_ARG, "descriptor is NULL");
   if (d->m < 1 || d->m > (int64_t(1) << 30)) return fail(NEDNER_E_ARG, "m must be in [1, 2^30]");
@@ -192,10 +209,11 @@ nedner_status validate_impl(const nedner_desc* d, Derived* out) {
   if (d->rows_per_wave < 0) return fail(NEDNER_E_ARG, "rows_per_wave must be >= 0");
   if (d->time_per_lane != 0 && d->time_per_lane != 1 && d->time_per_lane != 2 && d->time_per_lane != 4)
     return fail(NEDNER_E_ARG, "time_per_lane must be 0, 1, 2 or 4");
-  if (d->flags & ~uint32_t(15)) return fail(NEDNER_E_ARG, "unknown flag bits");
+  if (d->flags & ~uint32_t(31)) return fail(NEDNER_E_ARG, "unknown flag bits");
   Derived v{};
-  v.n1 = scaled_size(d->sigma, d->n1);
-  v.n2 = scaled_size(d->sigma, d->n2);
+  v.equi = (d->flags & NEDNER_EQUISPACED) != 0;
+  v.n1 = v.equi ? d->n1 : scaled_size(d->sigma, d->n1);
+  v.n2 = v.equi ? d->n2 : scaled_size(d->sigma, d->n2);
   v.ntt = scaled_size(d->sigma, d->nt);
   if (v.n1 < 0 || v.n2 < 0 || v.ntt < 0 || (v.n1 % 2) || (v.n2 % 2) || (v.ntt % 2))
     return fail(NEDNER_E_ARG, "sigma * n1, sigma * n2 and sigma * nt must be even integers");
@@ -228,6 +246,18 @@ nedner_status validate_impl(const nedner_desc* d, Derived* out) {
       const double h = d->h[m];
       if (!finite(h) || h < 0) return fail(NEDNER_E_ARG, "detector area must be finite and >= 0 at index " + std::to_string(m));
     }
+  }
+  if (v.equi) {
+    std::vector<int64_t> nodes(d->m);
+    for (int64_t m = 0; m < d->m; ++m) {
+      long i[2];
+      if (!grid_node(*d, v, m, i))
+        return fail(NEDNER_E_ARG, "sensor " + std::to_string(m) + " is not on a grid node (NEDNER_EQUISPACED)");
+      nodes[m] = int64_t(i[0]) * d->n2 + i[1];
+    }
+    std::sort(nodes.begin(), nodes.end());
+    if (std::adjacent_find(nodes.begin(), nodes.end()) != nodes.end())
+      return fail(NEDNER_E_ARG, "two sensors on one grid node (NEDNER_EQUISPACED)");
   }
   // frequencies: |omega| dt over the mode set (both Nyquist representatives)
   {
@@ -275,10 +305,26 @@ struct Geometry {
   std::vector<int> ent_m;
   std::vector<double> ent_w2;
   std::vector<int> cellbeg;     // [n2 * nseg][CB]
+  std::vector<int> node;        // equispaced: [n1 * n2] sensor at each node, -1 where none
+  std::vector<double> s;        // equispaced: [M] h_m / (d1 d2)
 };
 
 void build_geometry(const nedner_desc& d, const Derived& v, Geometry& G) {
   const int64_t M = d.m;
+  if (v.equi) {
+    G.cell.resize(2 * M);
+    G.s.resize(M);
+    G.node.assign((size_t)d.n1 * d.n2, -1);
+    for (int64_t m = 0; m < M; ++m) {
+      long i[2] = {0, 0};
+      grid_node(d, v, m, i);
+      G.cell[2 * m] = int(i[0]);
+      G.cell[2 * m + 1] = int(i[1]);
+      G.s[m] = (d.h ? d.h[m] : v.L1 * v.L2 / double(M)) / (d.d1 * d.d2);
+      G.node[(size_t)i[0] * d.n2 + i[1]] = int(m);
+    }
+    return;
+  }
   const int W = v.W, h = W / 2 - 1;
   const bool plain = d.prec == NEDNER_FP32_PLAIN;
   G.cell.resize(2 * M);
@@ -627,8 +673,9 @@ nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* ou
 
   // deconvolution and precorrection tables
   std::vector<double> d1(v.J1), d2(v.K2), dtb(desc->nt);
-  for (int je = 0; je < v.J1; ++je) d1[je] = 1.0 / window_phihat(v, je - desc->n1 / 2, double(v.n1));
-  for (int k2 = 0; k2 < v.K2; ++k2) d2[k2] = 1.0 / window_phihat(v, k2, double(v.n2));
+  // no lateral window on the equispaced path: the lateral DFT is exact
+  for (int je = 0; je < v.J1; ++je) d1[je] = v.equi ? 1.0 : 1.0 / window_phihat(v, je - desc->n1 / 2, double(v.n1));
+  for (int k2 = 0; k2 < v.K2; ++k2) d2[k2] = v.equi ? 1.0 : 1.0 / window_phihat(v, k2, double(v.n2));
   for (int64_t n = 0; n < desc->nt; ++n) dtb[n] = 1.0 / window_phihat(v, double(n - desc->nt / 2), double(v.ntt));
 
   DevAlloc A;
@@ -655,6 +702,11 @@ nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* ou
   k.w1 = wide ? A.upload(G.w1) : A.upload_as<float>(G.w1);
   k.w2 = wide ? A.upload(G.w2) : A.upload_as<float>(G.w2);
   k.cell = static_cast<const int*>(A.upload(G.cell));
+  k.equi = v.equi;
+  if (v.equi) {
+    k.node = static_cast<const int*>(A.upload(G.node));
+    k.sw = dbl ? A.upload(G.s) : A.upload_as<float>(G.s);
+  }
   {
     DevAlloc Lst;
     const ListTables t = upload_lists(G, wide, Lst);
@@ -747,14 +799,14 @@ nedner_status forward_impl(nedner_plan plan, const void* d_g, void* d_out, int k
   if (kind == NEDNER_STAGE_GRID) {
     Marks mk(plan, s, 1, "spread");
     NEDNER_RUN(mk.mark(), "event");
-    NEDNER_RUN(nedner::launch_spread(k, d_g, d_out, s), "spread");
+    NEDNER_RUN(k.equi ? nedner::launch_place(k, d_g, d_out, s) : nedner::launch_spread(k, d_g, d_out, s), "spread");
     NEDNER_RUN(mk.mark(), "event");
     return NEDNER_OK;
   }
   const bool spec = kind == NEDNER_SPECTRUM_COMPLEX;
   Marks mk(plan, s, spec ? 4 : 6, spec ? kSpecNames : kFwdNames);
   NEDNER_RUN(mk.mark(), "event");
-  NEDNER_RUN(nedner::launch_spread(k, d_g, b0, s), "spread");
+  NEDNER_RUN(k.equi ? nedner::launch_place(k, d_g, b0, s) : nedner::launch_spread(k, d_g, b0, s), "spread");
   NEDNER_RUN(mk.mark(), "event");
   NEDNER_RUN(nedner::launch_lat_a(k, b0, b1, s), "lateral FFT (second axis)");
   NEDNER_RUN(mk.mark(), "event");
@@ -781,7 +833,7 @@ nedner_status adjoint_impl(nedner_plan plan, const void* d_in, int kind, void* d
   if (kind == NEDNER_STAGE_GRID) {
     Marks mk(plan, s, 1, "gather");
     NEDNER_RUN(mk.mark(), "event");
-    NEDNER_RUN(nedner::launch_gather(k, d_in, d_g, s), "gather");
+    NEDNER_RUN(k.equi ? nedner::launch_place_adj(k, d_in, d_g, s) : nedner::launch_gather(k, d_in, d_g, s), "gather");
     NEDNER_RUN(mk.mark(), "event");
     return NEDNER_OK;
   }
@@ -797,7 +849,7 @@ nedner_status adjoint_impl(nedner_plan plan, const void* d_in, int kind, void* d
   NEDNER_RUN(mk.mark(), "event");
   NEDNER_RUN(nedner::launch_adj_a(k, b1, b0, s), "adjoint lateral FFT (second axis)");
   NEDNER_RUN(mk.mark(), "event");
-  NEDNER_RUN(nedner::launch_gather(k, b0, d_g, s), "gather");
+  NEDNER_RUN(k.equi ? nedner::launch_place_adj(k, b0, d_g, s) : nedner::launch_gather(k, b0, d_g, s), "gather");
   NEDNER_RUN(mk.mark(), "event");
   return NEDNER_OK;
 }
@@ -839,8 +891,10 @@ nedner_status create_batch(const nedner_desc* descs, int count, int device, nedn
   const int prec = descs[0].prec, w = descs[0].w;
   bool all4 = true;
   for (int i = 0; i < count; ++i) {
-    if (descs[i].prec != prec || descs[i].w != w)
-      return fail(NEDNER_E_ARG, "all problems of a batch must share precision and window width");
+    if (descs[i].prec != prec || descs[i].w != w || descs[i].window != descs[0].window)
+      return fail(NEDNER_E_ARG, "all problems of a batch must share precision, window and window width");
+    if (descs[i].flags & NEDNER_EQUISPACED)
+      return fail(NEDNER_E_UNSUPPORTED, "batched plans do not take NEDNER_EQUISPACED");
     if (descs[i].nt % 4) all4 = false;
   }
   // the spreading kernel's time-per-lane is a compile-time shape: one for the batch
@@ -1148,7 +1202,7 @@ nedner_status autotune_single(nedner_plan p, const void* d_g, hipStream_t s, ned
   if (!p->ws || p->ws_bytes < p->need_ws) return fail(NEDNER_E_WORKSPACE, "autotune needs the workspace");
   if (!d_g) return fail(NEDNER_E_ARG, "autotune needs a data array");
   double ms_spread = 0;
-  nedner_status st = tune_spread(p, d_g, p->ws, s, 0, &ms_spread);
+  nedner_status st = p->kp.equi ? NEDNER_OK : tune_spread(p, d_g, p->ws, s, 0, &ms_spread);
   if (st != NEDNER_OK) return st;
   void* vol = nullptr;
   const size_t vb = (size_t)p->kp.N1 * p->kp.N2 * p->kp.N3 * (p->kp.prec == NEDNER_FP64 ? 8 : 4);

@@ -289,10 +289,13 @@ __device__ __forceinline__ void adj_b_body(const KP& p, int TB, int bx, int by, 
   stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
     const int k1 = i >> lsh, nn = nb + (i & (TB - 1));
     cpx<R> z = {R(0), R(0)};
-    const int j1 = k1 < n / 2 ? k1 : k1 - n;
-    if (nn < Nt && j1 >= -h1 && j1 <= h1) {
-      const int je = j1 + h1;
-      z = G[((size_t)k2 * p.J1 + je) * Nt + nn] * (d1[je] * d2 * dt[nn]);
+    if (nn < Nt) {
+      // bin k1 holds the kept modes j1 = k1 and j1 = k1 - n that lie in
+      // [-N1/2, N1/2]: one of them on the oversampled grid, both of the
+      // Nyquist pair at k1 = N1/2 when n = N1 (the equispaced path)
+      const R f = d2 * dt[nn];
+      if (k1 <= h1) z = G[((size_t)k2 * p.J1 + k1 + h1) * Nt + nn] * (d1[k1 + h1] * f);
+      if (k1 - n >= -h1) z = z + G[((size_t)k2 * p.J1 + k1 - n + h1) * Nt + nn] * (d1[k1 - n + h1] * f);
     }
     return z;
   });
@@ -324,8 +327,10 @@ __device__ __forceinline__ void adj_a_body(const KP& p, int TB, int bx, int by, 
     const int k = i >> lsh, pr = pb + (i & (TB - 1));
     cpx<R> c = {R(0), R(0)};
     if (pr < npairs) {
-      if (k == 0) {
-        const cpx<R> a = src[2 * pr], b = src[2 * pr + 1];
+      if (k == 0 || (k == h2 && 2 * h2 == n)) {
+        // real bins (k = 0, and the Nyquist bin n/2 when it is kept, n = N2):
+        // the two half-spectrum terms of the forward fall on one bin
+        const cpx<R> a = src[(size_t)k * p.Nt + 2 * pr], b = src[(size_t)k * p.Nt + 2 * pr + 1];
         c = {a.x, b.x};
       } else if (k <= h2) {
         const cpx<R> a = src[(size_t)k * p.Nt + 2 * pr], b = src[(size_t)k * p.Nt + 2 * pr + 1];

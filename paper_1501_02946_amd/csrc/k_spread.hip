@@ -599,6 +599,55 @@ hipError_t launch_spread_many(const KP& p0, const BatchProb* bp, const WorkList&
 }
 
 // ---------------------------------------------------------------------------
+// Sensors on the output grid (the equispaced, NER-only case): the lateral
+// sums of eq. (5) are a plain DFT of the node grid, so the spreading becomes
+// a placement, U[q1][q2][n] = s_m g[m][n] at the sensor's node and zero at
+// the other nodes, and its transpose a pick-up. One workgroup per (node or
+// sensor, 256 samples), coalesced along time.
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_place(KP p, int tchunks, const R* __restrict__ g, R* __restrict__ U) {
+  const long nd = blockIdx.x / tchunks;
+  const int t = (blockIdx.x % tchunks) * 256 + threadIdx.x;
+  if (t >= p.Nt) return;
+  const int m = p.node[nd];
+  U[nd * p.Nt + t] = m >= 0 ? static_cast<const R*>(p.sw)[m] * g[(size_t)m * p.Nt + t] : R(0);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_place_adj(KP p, int tchunks, const R* __restrict__ U, R* __restrict__ g) {
+  const long m = blockIdx.x / tchunks;
+  const int t = (blockIdx.x % tchunks) * 256 + threadIdx.x;
+  if (t >= p.Nt) return;
+  const size_t nd = (size_t)p.cell[2 * m] * p.n2 + p.cell[2 * m + 1];
+  g[m * p.Nt + t] = static_cast<const R*>(p.sw)[m] * U[nd * p.Nt + t];
+}
+
+hipError_t launch_place(const KP& p, const void* g, void* U, hipStream_t s) {
+  const int tch = (p.Nt + 255) / 256;
+  const dim3 grid((unsigned)((long)p.n1 * p.n2 * tch));
+  if (p.prec == PREC_FP64)
+    hipLaunchKernelGGL(k_place<double>, grid, dim3(256), 0, s, p, tch, static_cast<const double*>(g),
+                       static_cast<double*>(U));
+  else
+    hipLaunchKernelGGL(k_place<float>, grid, dim3(256), 0, s, p, tch, static_cast<const float*>(g),
+                       static_cast<float*>(U));
+  return hipGetLastError();
+}
+
+hipError_t launch_place_adj(const KP& p, const void* U, void* g, hipStream_t s) {
+  const int tch = (p.Nt + 255) / 256;
+  const dim3 grid((unsigned)((long)p.M * tch));
+  if (p.prec == PREC_FP64)
+    hipLaunchKernelGGL(k_place_adj<double>, grid, dim3(256), 0, s, p, tch, static_cast<const double*>(U),
+                       static_cast<double*>(g));
+  else
+    hipLaunchKernelGGL(k_place_adj<float>, grid, dim3(256), 0, s, p, tch, static_cast<const float*>(U),
+                       static_cast<float*>(g));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // occupancy of the forward spreading instance a plan launches (aligned data)
 
 template <typename R, typename WT, typename A, int W, int TT>

@@ -35,6 +35,7 @@ struct KP {
   int pass_threads; // FFT passes: threads per workgroup (multiple of 64, <= 512)
   int pass_ip;    // FFT passes: in-place (1) or ping-pong (0) transform
   int window;     // 0: Gaussian exp(-beta x^2); 1: Kaiser-Bessel I0(beta sqrt(1 - (2x/W)^2))
+  int equi;       // sensors on the output grid: placement instead of spreading, n1 = N1, n2 = N2
 
   // ---- window and frequency constants (double, reduced on the host) -----
   double beta;      // window parameter (see window), x in grid units, all three axes
@@ -54,6 +55,8 @@ struct KP {
   const int* ent_m;    // spreading list: sensor of each entry
   const void* ent_w2;  // spreading list: second-axis weight of each entry
   const int* cellbeg;  // [n2 * nseg][CB] list offsets per sweep cell
+  const int* node;     // equispaced: [n1 * n2] sensor at each node, -1 where none
+  const void* sw;      // equispaced: [M] real: h_m / (d1 d2)
   const void* dec1;    // [J1] real: 1/phihat_1(j1), j1 = -N1/2..N1/2
   const void* dec2;    // [K2] real: 1/phihat_2(k2), k2 = 0..N2/2
   const void* dect;    // [Nt] real: 1/phihat_t(n - Nt/2)
@@ -101,6 +104,9 @@ inline hipError_t allow_smem(F kernel, size_t bytes) {
 // Host launchers (defined in the .hip files). All enqueue on `s` and return
 // the launch status.
 hipError_t launch_spread(const KP& p, const void* g, void* U, hipStream_t s);
+// Equispaced sensors: U at each node = s_m g[m] (zero where no sensor), and its transpose.
+hipError_t launch_place(const KP& p, const void* g, void* U, hipStream_t s);
+hipError_t launch_place_adj(const KP& p, const void* U, void* g, hipStream_t s);
 // Workgroups of the forward spreading kernel (prec, W, TT, spread_pd, wide_w of p) per CU.
 int spread_blocks_per_cu(const KP& p);
 hipError_t launch_gather(const KP& p, const void* U, void* g, hipStream_t s);

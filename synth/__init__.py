@@ -17,6 +17,12 @@ Workload recipes (all with sound speed c = 1 and aperture [0,1)^2):
   cylinders; output 256x256x512.
 * ``c5``: 192x192 sensors jittered by +/-0.4, 768 samples, 20 balls, 1 % noise;
   output 192x192x384.
+* ``c6``: the equi-steradian mask of App. A: ~1625 sensors snapped to a
+  240x240 grid, centre of interest 0.265 above the aperture centre, weights
+  h_m ~ r^3; 512 samples, 10 balls, 1 % noise; output 240x240x256.
+* ``c7``: 128x128 sensors on the nodes of the 128x128 output grid (the
+  equispaced, NER-only case), 512 samples, 10 balls, 1 % noise; output
+  128x128x256.
 * ``c4``: 64 problems, M uniform in [1024, 16384] kept from a ceil(sqrt(M))^2
   jittered grid, Nt in {256, 512, 1024}, 1-10 balls each, output s x s x Nt/2
   with s the smallest even 5-smooth integer >= ceil(sqrt(M)) (the mode sets
@@ -34,7 +40,7 @@ import numpy as np
 __all__ = [
     "Problem", "jittered_grid", "density_sensors", "random_balls",
     "bead_chain", "ball_signal", "add_noise", "make_problem", "config",
-    "five_smooth_at_least", "batch_c4",
+    "five_smooth_at_least", "batch_c4", "equi_steradian", "steradian_weights",
 ]
 
 
@@ -236,12 +242,119 @@ def config(name: str, seed: int = 0) -> Problem:
         m = xy.shape[0]
         return make_problem(xy, np.full(m, 1.0 / m), balls, 768, 192, 192, 384,
                             rng=rng, noise=0.01, name=name)
+    if name == "c6":
+        # the sparse equi-steradian mask: ~1625 sensors on a 240x240 scanned
+        # grid (stand-in for the paper's 226x226, whose doubled size is not
+        # 5-smooth), centre of interest 0.265 of the aperture off the plane
+        xy, _ = equi_steradian(1625, 0.265, grid=240)
+        h = steradian_weights(xy, 0.265)
+        balls = random_balls(10, rng)
+        return make_problem(xy, h, balls, 512, 240, 240, 256, rng=rng, noise=0.01, name=name)
+    if name == "c6sub":
+        xy, _ = equi_steradian(200, 0.265, grid=48)
+        h = steradian_weights(xy, 0.265)
+        balls = random_balls(3, rng)
+        return make_problem(xy, h, balls, 96, 48, 48, 48, name=name)
+    if name == "c7":
+        # the NER-only case: 128x128 sensors exactly on the nodes of the
+        # 128x128 output grid (c2's data on an equispaced grid)
+        i = np.arange(128) / 128.0
+        xy = np.stack(np.meshgrid(i, i, indexing="ij"), -1).reshape(-1, 2)
+        balls = random_balls(10, rng)
+        m = xy.shape[0]
+        return make_problem(xy, np.full(m, 1.0 / m), balls, 512, 128, 128, 256,
+                            rng=rng, noise=0.01, name=name)
     if name == "c5sub":
         xy = jittered_grid(16, 0.4, rng)
         balls = random_balls(3, rng)
         return make_problem(xy, np.full(256, 1.0 / 256), balls, 64, 16, 16, 32,
                             name=name)
     raise KeyError(name)
+
+
+def equi_steradian(n_target: int, r0: float, length: float = 1.0, grid: int = 0,
+                   center=None, ratio: float = 1.8):
+    """Equi-steradian sensor arrangement of the paper's App. A, as rings.
+
+    Seen from a centre of interest at height r0 above the middle of a square
+    aperture of side `length`, the cap of polar angles up to theta_max =
+    atan((length/2)/r0) (the circle inscribed in the aperture) is cut into
+    rings of equal solid angle per sensor, omega = 2 pi (1 - cos theta_max) /
+    n_target. The pole holds one sensor (its cap is one omega). Ring k holds
+    j_k sensors, a power of two, and spans polar angles with
+    2 pi (cos theta_{k-1} - cos theta_k) = omega j_k; j_k starts at the count
+    of the ring before and doubles while the chord between neighbours on the
+    ring exceeds `ratio` times the distance to the nearest sensor of the ring
+    before (points on the unit sphere). Sensors sit at the mid polar angle of
+    their ring, at azimuths 2 pi i / j_k + pi / j_k + phi_r, phi_r carried
+    over from the ring before (its first azimuth plus (k-1) 2 pi / j_{k-1}),
+    and are projected from the centre onto the plane. Rings stop at
+    theta_max. With `grid` > 0 every sensor is moved to the nearest node of a
+    grid x grid lattice of cell centres (duplicates dropped), as for a mask on
+    a scanned sensor grid.
+
+    Returns (xy, rings): positions (M, 2) in [0, length)^2 and a list of
+    (theta_lo, theta_hi, count) per ring, pole first.
+    """
+    c = (0.5 * length, 0.5 * length) if center is None else center
+    theta_max = math.atan(0.5 * length / r0)
+    omega = 2.0 * math.pi * (1.0 - math.cos(theta_max)) / n_target
+    th_prev = math.acos(1.0 - omega / (2.0 * math.pi))
+    pts = [(0.0, 0.0)]
+    rings = [(0.0, th_prev, 1)]
+    prev_pts = np.array([[0.0, 0.0, 1.0]])
+    j, phi_prev0, k = 1, 0.0, 1
+
+    def unit(theta, phi):
+        return np.stack([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi),
+                         np.full_like(phi, np.cos(theta))], axis=-1)
+
+    while True:
+        k += 1
+        jk = max(j, 2)
+        while True:
+            cos_hi = math.cos(th_prev) - omega * jk / (2.0 * math.pi)
+            if cos_hi <= -1.0:
+                break
+            th_hi = math.acos(cos_hi)
+            th_mid = 0.5 * (th_prev + th_hi)
+            phi_r = phi_prev0 + (k - 1) * 2.0 * math.pi / j
+            phis = 2.0 * math.pi * np.arange(jk) / jk + math.pi / jk + phi_r
+            ring = unit(th_mid, phis)
+            chord = 2.0 * math.sin(th_mid) * math.sin(math.pi / jk)
+            nearest = np.min(np.linalg.norm(ring[:1, None, :] - prev_pts[None, :, :], axis=-1))
+            if chord > ratio * nearest:
+                jk *= 2
+                continue
+            break
+        if cos_hi <= -1.0 or th_hi > theta_max:
+            break
+        for ph in phis:
+            pts.append((th_mid, ph))
+        rings.append((th_prev, th_hi, jk))
+        prev_pts, j, phi_prev0, th_prev = ring, jk, float(phis[0]), th_hi
+    pol = np.array([q[0] for q in pts])
+    az = np.array([q[1] for q in pts])
+    rho = r0 * np.tan(pol)
+    xy = np.stack([c[0] + rho * np.cos(az), c[1] + rho * np.sin(az)], axis=1)
+    inside = np.all((xy >= 0.0) & (xy < length), axis=1)
+    xy = xy[inside]
+    if grid > 0:
+        step = length / grid
+        idx = np.clip(np.floor(xy / step).astype(np.int64), 0, grid - 1)
+        idx = np.unique(idx, axis=0)
+        xy = (idx + 0.5) * step
+    return np.ascontiguousarray(xy), rings
+
+
+def steradian_weights(xy: np.ndarray, r0: float, length: float = 1.0, center=None) -> np.ndarray:
+    """Detector weights h_m proportional to r^3, r the distance from the sensor
+    to the centre of interest (paper, Sec. 5, weighting term), scaled so that
+    they sum to the aperture area."""
+    c = (0.5 * length, 0.5 * length) if center is None else center
+    r = np.sqrt((xy[:, 0] - c[0]) ** 2 + (xy[:, 1] - c[1]) ** 2 + r0 * r0)
+    h = r ** 3
+    return h * (length * length / h.sum())
 
 
 def batch_c4(seed: int = 0, count: int = 64):
