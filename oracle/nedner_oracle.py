@@ -39,7 +39,7 @@ import numpy as np
 __all__ = ["Geometry", "geometry", "mode_numbers", "wavenumbers", "omega",
            "weight", "ned", "ner", "spectrum", "volume_from_spectrum",
            "forward", "adjoint", "brute_spectrum", "brute_volume",
-           "brute_matrix"]
+           "brute_matrix", "spectrum_at"]
 
 # Memory cap for one block of the exponential matrix (complex128 entries).
 _BLOCK_ENTRIES = 1 << 24
@@ -181,6 +181,35 @@ def spectrum(xy, h, g, geo: Geometry) -> np.ndarray:
     G = ned(xy, h, g, geo)
     H = ner(G, geo)
     return (geo.dt / geo.d3) * weight(geo) * H
+
+
+def spectrum_at(xy, h, g, geo: Geometry, modes) -> np.ndarray:
+    """F(j,l) of eq. (5) at the listed modes only, for workloads whose whole
+    spectrum is too large to evaluate here.
+
+    `modes` is (S, 3) of storage indices (i1, i2, i3) into the (N1, N2, N3)
+    mode grid in FFT order. The sums are those of `ned`, `ner` and `weight`
+    restricted to the listed (j, l): the lateral exponential of each listed
+    j against every sensor (one product with the data), then the time sum
+    with the exact exponential of omega(j,l) t_n. Returns complex128 (S,).
+    """
+    modes = np.asarray(modes, dtype=np.int64).reshape(-1, 3)
+    k1, k2, kz = wavenumbers(geo)
+    K1, K2, KZ = k1[modes[:, 0]], k2[modes[:, 1]], kz[modes[:, 2]]
+    xy = np.asarray(xy, dtype=np.float64)
+    s = np.asarray(h, dtype=np.float64) / (geo.d1 * geo.d2)
+    sg = s[:, None] * np.asarray(g, dtype=np.float64)
+    ph = K1[:, None] * (xy[None, :, 0] - geo.a1) + K2[:, None] * (xy[None, :, 1] - geo.a2)
+    G = np.cos(ph) @ sg - 1j * (np.sin(ph) @ sg)                   # (S, Nt)
+    kk = np.sqrt(K1 ** 2 + K2 ** 2 + KZ ** 2)
+    om = geo.c * np.sign(KZ) * kk
+    tn = geo.t0 + geo.dt * np.arange(geo.nt)
+    H = np.sum(G * np.exp(-1j * om[:, None] * tn[None, :]), axis=1)
+    W = np.zeros(len(modes))
+    nz = KZ != 0.0
+    W[nz] = 2.0 * geo.c * np.abs(KZ[nz]) / kk[nz]
+    W[(KZ == 0.0) & (kk == 0.0)] = 2.0 * geo.c
+    return (geo.dt / geo.d3) * W * H
 
 
 def volume_from_spectrum(F: np.ndarray) -> np.ndarray:

@@ -322,3 +322,17 @@ def test_golden_tiny_case_regression():
     assert np.abs(F - d["F"]).max() <= 1e-12 * np.abs(d["F"]).max()
     v = O.forward(d["xy"], d["h"], d["g"], geo)
     assert np.abs(v - d["v"]).max() <= 1e-12 * np.abs(d["v"]).max()
+
+
+@pytest.mark.parametrize("name", ["c1", "c5sub"])
+def test_sampled_spectrum_equals_full_spectrum(name):
+    """The restricted sums at listed modes equal the full spectrum there."""
+    p = synth.config(name)
+    geo = O.geometry(**p.geometry_kwargs())
+    F = O.spectrum(p.xy, p.h, p.g, geo)
+    rng = np.random.default_rng(4)
+    modes = np.stack([rng.integers(0, n, 40) for n in (p.n1, p.n2, p.n3)], axis=1)
+    modes = np.concatenate([modes, [[0, 0, 0], [p.n1 // 2, p.n2 // 2, p.n3 // 2], [0, 0, 5]]])
+    Fs = O.spectrum_at(p.xy, p.h, p.g, geo, modes)
+    ref = F[modes[:, 0], modes[:, 1], modes[:, 2]]
+    assert np.max(np.abs(Fs - ref)) <= 1e-11 * np.max(np.abs(ref))
