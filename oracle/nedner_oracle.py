@@ -28,6 +28,17 @@ Readings of the paper used here (the paper is garbled or silent on them):
 
 The adjoint is taken with respect to the real Euclidean inner products on data
 (M x Nt) and volume (N1 x N2 x N3), so that autograd semantics hold.
+
+It also evaluates the forward operator Q of Sec. 2 (initial pressure -> the
+trace of the wave equation's solution on the sensor plane) for a volume on the
+voxel grid, taken as periodic: each Fourier mode of the volume oscillates as
+cos(c |K| t) (the solution with p(., 0) = f and d/dt p(., 0) = 0), so
+
+    trace     (Q v)[m,n] = Re sum_{j,l} V(j,l) cos(c |K(j,l)| t_n) exp(i k.(y_m - a)),
+              V = DFT_3(v) / (N1 N2 N3),
+
+and its adjoint. These sums are exact for the periodic grid model; they carry
+no sensor weight h_m and no inversion weight.
 """
 from __future__ import annotations
 
@@ -39,7 +50,8 @@ import numpy as np
 __all__ = ["Geometry", "geometry", "mode_numbers", "wavenumbers", "omega",
            "weight", "ned", "ner", "spectrum", "volume_from_spectrum",
            "forward", "adjoint", "brute_spectrum", "brute_volume",
-           "brute_matrix", "spectrum_at"]
+           "brute_matrix", "spectrum_at", "trace", "trace_adjoint",
+           "brute_trace"]
 
 # Memory cap for one block of the exponential matrix (complex128 entries).
 _BLOCK_ENTRIES = 1 << 24
@@ -258,6 +270,62 @@ def adjoint(v, xy, h, geo: Geometry) -> np.ndarray:
     return s[:, None] * out
 
 
+def _abs_k(geo: Geometry) -> np.ndarray:
+    """|K(j,l)| on the (N1, N2, N3) mode grid, FFT order."""
+    k1, k2, kz = wavenumbers(geo)
+    return np.sqrt(k1[:, None, None] ** 2 + k2[None, :, None] ** 2
+                   + kz[None, None, :] ** 2)
+
+
+def trace(v, xy, geo: Geometry) -> np.ndarray:
+    """Forward operator Q of Sec. 2 on the periodic voxel grid: volume -> (M, Nt).
+
+    (Q v)[m,n] = Re sum_j exp(+i k_j.(y_m - a)) R(j,n), with
+    R(j,n) = sum_l V(j,l) cos(c |K(j,l)| t_n) and V = DFT_3(v)/(N1 N2 N3):
+    the wave equation's solution for the initial pressure v (initial velocity
+    zero), mode by mode, evaluated on the sensor plane z = 0 at the sensors.
+    The cosine is evaluated directly for each t_n.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    n_all = geo.n1 * geo.n2 * geo.n3
+    V = np.fft.fftn(v) / n_all
+    kk = _abs_k(geo)
+    R = np.empty((geo.n1, geo.n2, geo.nt), dtype=np.complex128)
+    for n in range(geo.nt):
+        t = geo.t0 + n * geo.dt
+        R[:, :, n] = (V * np.cos(geo.c * kk * t)).sum(axis=2)
+    xy = np.asarray(xy, dtype=np.float64)
+    e1, e2 = _lateral_factors(xy, geo)
+    m = xy.shape[0]
+    out = np.zeros((m, geo.nt))
+    rows = max(1, _BLOCK_ENTRIES // max(1, geo.n2 * m))
+    for r0 in range(0, geo.n1, rows):
+        r1 = min(geo.n1, r0 + rows)
+        e = (e1[r0:r1, None, :] * e2[None, :, :]).reshape(-1, m)
+        r = R[r0:r1].reshape(-1, geo.nt)
+        er, ei = np.ascontiguousarray(e.real), np.ascontiguousarray(e.imag)
+        rr, ri = np.ascontiguousarray(r.real), np.ascontiguousarray(r.imag)
+        # Re(conj(e)^T r) with e = exp(-i k.y)
+        out += er.T @ rr + ei.T @ ri
+    return out
+
+
+def trace_adjoint(d, xy, geo: Geometry) -> np.ndarray:
+    """Adjoint of `trace` for the real inner products: (M, Nt) -> volume.
+
+    G(j,n) = sum_m d[m,n] exp(-i k_j.(y_m - a)) (the lateral sum of `ned`
+    with unit sensor weights); C(j,l) = sum_n G(j,n) cos(c |K(j,l)| t_n);
+    result Re IDFT_3(C) with the 1/(N1 N2 N3) of the inverse DFT.
+    """
+    G = ned(xy, np.full(len(xy), geo.d1 * geo.d2), d, geo)
+    kk = _abs_k(geo)
+    C = np.zeros((geo.n1, geo.n2, geo.n3), dtype=np.complex128)
+    for n in range(geo.nt):
+        t = geo.t0 + n * geo.dt
+        C += G[:, :, n, None] * np.cos(geo.c * kk * t)
+    return np.fft.ifftn(C).real
+
+
 # --------------------------------------------------------------------------
 # Brute force: every term of eq. (5) with its own exponential, no factorising,
 # no Horner, no FFT. For tiny inputs only; it checks the routines above.
@@ -324,3 +392,31 @@ def brute_matrix(xy, h, geo: Geometry) -> np.ndarray:
         F = brute_spectrum(xy, h, e.reshape(m, geo.nt), geo)
         cols.append(brute_volume(F).ravel())
     return np.stack(cols, axis=1)
+
+
+def brute_trace(v, xy, geo: Geometry) -> np.ndarray:
+    """Q v term by term: an explicit DFT of the volume per mode, then one
+    cosine and one lateral exponential per (m, n, j, l). Tiny inputs only."""
+    v = np.asarray(v, dtype=np.float64)
+    j1s, j2s, ls = _brute_modes(geo)
+    i1 = np.arange(geo.n1)[:, None, None]
+    i2 = np.arange(geo.n2)[None, :, None]
+    i3 = np.arange(geo.n3)[None, None, :]
+    n_all = geo.n1 * geo.n2 * geo.n3
+    m = len(xy)
+    out = np.zeros((m, geo.nt))
+    for j1 in j1s:
+        for j2 in j2s:
+            for l in ls:
+                coef = (v * np.exp(-2j * math.pi * (j1 * i1 / geo.n1 + j2 * i2 / geo.n2
+                                                    + l * i3 / geo.n3))).sum() / n_all
+                k1 = 2.0 * math.pi * j1 / geo.l1
+                k2 = 2.0 * math.pi * j2 / geo.l2
+                kz = 2.0 * math.pi * l / (geo.n3 * geo.d3)
+                kk = math.sqrt(k1 * k1 + k2 * k2 + kz * kz)
+                for mm in range(m):
+                    lat = np.exp(1j * (k1 * (xy[mm, 0] - geo.a1) + k2 * (xy[mm, 1] - geo.a2)))
+                    for n in range(geo.nt):
+                        t = geo.t0 + n * geo.dt
+                        out[mm, n] += (coef * math.cos(geo.c * kk * t) * lat).real
+    return out
