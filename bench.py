@@ -11,6 +11,9 @@ resident batch of synthetic sensor data. Prints ONE JSON line:
   cpu_baseline the FP64 oracle timed on the host on the same workload
   fp64_plain   the same operator in FP64 on the GPU, and the FP32 speedup
   kaiser_bessel_w8  the same workload with the Kaiser-Bessel window at 8 taps
+  forward_model_q   the forward operator Q of the wave equation (volume -> data)
+               and its adjoint on the same plan, per-stage times, and sampled
+               outputs of Q against the oracle
 
 Inputs: 128x128 jittered sensors (+/-0.45 pitch), 512 samples, 10 random balls
 and 1 % noise, output 128x128x256 (the FP32-vs-plain comparison workload).
@@ -148,10 +151,16 @@ def summarize_counters(root, workload, prec, tuning):
 
 
 def time_steps(torch, plan, g, out, steps, warmup, profile=False):
+    return time_op(torch, plan, lambda: plan.forward(g, out=out), steps, warmup, profile)
+
+
+def time_op(torch, plan, fn, steps, warmup, profile=False):
+    """Mean time of fn() (one operator call on the plan's stream) over `steps`
+    calls, HIP events around them; with profile, the plan's stage times too."""
     import ctypes
     import paper_1501_02946_amd as N
     for _ in range(warmup):
-        plan.forward(g, out=out)
+        fn()
     torch.cuda.synchronize()
     if profile:
         N._check(N.lib().nedner_profile_begin(plan._plan, steps))
@@ -160,7 +169,7 @@ def time_steps(torch, plan, g, out, steps, warmup, profile=False):
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
     for _ in range(steps):
-        plan.forward(g, out=out)
+        fn()
     t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
@@ -193,6 +202,25 @@ def cpu_baseline(p, leg_limit_s=60.0):
                    sample=(f"the full workload ({p.m} sensors x {p.nt} samples -> "
                            f"{p.n1}x{p.n2}x{p.n3}): NED as BLAS GEMMs on {threads} threads, "
                            "NER by Horner's rule (numpy, one thread), numpy ifftn"))
+
+
+def q_sample_error(p, vol, dq, nsens=48, ntimes=4, seed=3):
+    """rel-L2 of Q's output at sampled (sensor, time) pairs against the oracle's
+    sums at those times (each time on its own: Q at t_n needs only t_n)."""
+    import dataclasses
+
+    import numpy as np
+    import oracle as O
+    geo = O.geometry(**p.geometry_kwargs())
+    rng = np.random.default_rng(seed)
+    ms = rng.choice(p.m, nsens, replace=False)
+    ns = np.sort(rng.choice(p.nt, ntimes, replace=False))
+    v = vol.astype(np.float64)
+    want = np.empty((nsens, ntimes))
+    for i, n in enumerate(ns):
+        want[:, i] = O.trace(v, p.xy[ms], dataclasses.replace(geo, nt=1, t0=geo.t0 + n * geo.dt))[:, 0]
+    got = dq[np.ix_(ms, ns)].astype(np.float64)
+    return float(np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300))
 
 
 def bench_batch(a, torch, N, synth):
@@ -279,6 +307,8 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-kb", action="store_true",
                     help="skip the Kaiser-Bessel (8-tap) leg timed beside the headline")
+    ap.add_argument("--no-q", action="store_true",
+                    help="skip the leg timing the forward operator Q and its adjoint")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
@@ -386,6 +416,22 @@ def main(argv=None):
                                        stages_ms={k: round(v, 5) for k, v in stkb.items()})
         volkb = okb.cpu().numpy()
         del pkb
+    qsample = None
+    if not a.no_q:
+        # the forward operator Q (initial pressure -> sensor traces) on the
+        # reconstructed volume, and its adjoint on the data
+        dq = torch.empty((p.m, p.nt), dtype=plan.dtype, device=plan.device)
+        vq = torch.empty_like(out)
+        msq, stq = time_op(torch, plan, lambda: plan.q(out, out=dq), a.steps, a.warmup)
+        _, stq = time_op(torch, plan, lambda: plan.q(out, out=dq), a.steps, 1, profile=True)
+        msqa, _ = time_op(torch, plan, lambda: plan.q_adjoint(g, out=vq), a.steps, a.warmup)
+        _, stqa = time_op(torch, plan, lambda: plan.q_adjoint(g, out=vq), a.steps, 1, profile=True)
+        res["forward_model_q"] = dict(
+            ms_per_step=round(msq, 5), value=round(points / (msq / 1e3) / 1e6, 2), unit="Mpts/s",
+            adjoint_ms_per_step=round(msqa, 5),
+            stages_ms={k: round(v, 5) for k, v in stq.items()},
+            adjoint_stages_ms={k: round(v, 5) for k, v in stqa.items()})
+        qsample = dq.cpu().numpy()
     if not a.no_cpu_baseline:
         vref, cb = cpu_baseline(p)
         res["cpu_baseline"] = cb
@@ -396,6 +442,8 @@ def main(argv=None):
         if volkb is not None:
             res["kaiser_bessel_w8"]["rel_l2_vs_oracle"] = float(
                 np.linalg.norm(volkb.astype(np.float64) - vref) / nrm)
+        if qsample is not None:
+            res["forward_model_q"]["sampled_rel_l2_vs_oracle"] = q_sample_error(p, vol, qsample)
     else:
         res["cpu_baseline"] = None
     print(json.dumps(res), flush=True)

@@ -194,6 +194,30 @@ nedner_status nedner_execute(nedner_plan plan, const void* d_g, void* d_out, int
 nedner_status nedner_execute_adjoint(nedner_plan plan, const void* d_in, int kind, void* d_g,
                                      void* stream);
 
+/* Forward operator Q of the wave equation (Sec. 2): initial pressure -> the
+   trace, at the sensors on the plane z = 0, of the solution of the wave
+   equation with sound speed c, p(., 0) = v and zero initial velocity, for the
+   volume taken as periodic on the voxel grid (period N_i d_i per axis):
+     g[m][n] = Re sum_{j,l} V(j,l) cos(c |K(j,l)| t_n) exp(i k_j.(y_m - a)),
+     V = DFT_3(v) / (N1 N2 N3),  t_n = t0 + n dt,
+   with the same modes, wavenumbers and window approximations as the plan's
+   reconstruction, no sensor weight h_m and no inversion weight. It runs the
+   plan's adjoint pipeline with each NER column averaged between l and -l
+   (cos(omega t) = (exp(i omega t) + exp(-i omega t))/2 and omega(-l) =
+   -omega(l)). d_v: device (N1, N2, N3) of the plan's data type, depth
+   fastest; d_g: device (m, nt) output. Needs the workspace; not for batched
+   plans (NEDNER_E_ARG). Asynchronous on `stream`. */
+nedner_status nedner_execute_q(nedner_plan plan, const void* d_v, void* d_g, void* stream);
+
+/* Adjoint of nedner_execute_q for the real Euclidean inner products: data
+   d_g (m, nt) -> volume d_v (N1, N2, N3),
+     v = Re IDFT_3(C),  C(j,l) = sum_n G(j,n) cos(c |K(j,l)| t_n),
+     G(j,n) = sum_m d_g[m][n] exp(-i k_j.(y_m - a)),
+   the plan's forward pipeline with unit sensor weights, the constant weight
+   1/(N1 N2 N3) and each column averaged between l and -l. Same buffers,
+   workspace and errors as nedner_execute_q. */
+nedner_status nedner_execute_q_adjoint(nedner_plan plan, const void* d_g, void* d_v, void* stream);
+
 /* Batched forward: arrays of `count` device pointers (see plan_create_many). */
 nedner_status nedner_execute_many(nedner_plan plan, const void* const* d_g,
                                   void* const* d_out, int kind, void* stream);

@@ -19,7 +19,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Plan", "BatchPlan", "NednerRecon", "NednerAdjoint", "NednerError", "lib", "lsq",
+__all__ = ["Plan", "BatchPlan", "NednerRecon", "NednerAdjoint", "NednerQ", "NednerError", "lib", "lsq",
            "power_norm", "PRECISIONS", "KINDS", "FLAGS", "desc_struct", "info_struct",
            "query"]
 
@@ -95,6 +95,8 @@ def _declare(L):
     L.nedner_execute.argtypes = [vp, vp, vp, i32, vp]
     L.nedner_execute_adjoint.argtypes = [vp, vp, i32, vp, vp]
     L.nedner_execute_many.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
+    L.nedner_execute_q.argtypes = [vp, vp, vp, vp]
+    L.nedner_execute_q_adjoint.argtypes = [vp, vp, vp, vp]
     L.nedner_destroy.argtypes = [vp]
     L.nedner_status_string.argtypes = [i32]
     L.nedner_status_string.restype = ctypes.c_char_p
@@ -292,6 +294,33 @@ class Plan:
                                                 ctypes.c_void_p(out.data_ptr()), self._stream()))
         return out
 
+    # -- forward operator Q of the wave equation ---------------------------
+    def q(self, v, out=None):
+        """Forward operator Q: initial pressure (N1, N2, N3) -> the trace of the
+        wave equation's solution at the sensors (M, Nt), on the periodic voxel
+        grid (per mode cos(c|K|t)); no sensor or inversion weights."""
+        torch = self._torch
+        v = self._check_in(v, self.volume, "v")
+        if out is None:
+            out = torch.empty((self.m, self.nt), dtype=self.dtype, device=self.device)
+        self._workspace()
+        with torch.cuda.device(self.device):
+            _check(lib().nedner_execute_q(self._plan, ctypes.c_void_p(v.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def q_adjoint(self, g, out=None):
+        """Adjoint of `q` for the real inner products: data (M, Nt) -> volume."""
+        torch = self._torch
+        g = self._check_in(g, (self.m, self.nt), "g")
+        if out is None:
+            out = torch.empty(self.volume, dtype=self.dtype, device=self.device)
+        self._workspace()
+        with torch.cuda.device(self.device):
+            _check(lib().nedner_execute_q_adjoint(self._plan, ctypes.c_void_p(g.data_ptr()),
+                                                  ctypes.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
     # -- launch shape -------------------------------------------------------
     @property
     def tuning(self) -> dict:
@@ -480,7 +509,19 @@ def _autograd():
         def backward(ctx, grad):
             return ctx.plan.forward(grad.contiguous()), None
 
-    return _Recon, _Adjoint
+    class _Q(torch.autograd.Function):
+        """g = Q v (the wave equation's trace); backward applies Q*."""
+
+        @staticmethod
+        def forward(ctx, v, plan):
+            ctx.plan = plan
+            return plan.q(v)
+
+        @staticmethod
+        def backward(ctx, grad):
+            return ctx.plan.q_adjoint(grad.contiguous()), None
+
+    return _Recon, _Adjoint, _Q
 
 
 class _Lazy:
@@ -496,39 +537,47 @@ class _Lazy:
 
 NednerRecon = _Lazy(0)
 NednerAdjoint = _Lazy(1)
+NednerQ = _Lazy(2)
 
 
-def power_norm(plan: Plan, iters: int = 10, seed: int = 0) -> float:
-    """Estimate ||A||^2 (largest eigenvalue of A A*) by power iteration."""
+def power_norm(plan: Plan, iters: int = 10, seed: int = 0, model: str = "adjoint") -> float:
+    """Estimate the squared norm of the least-squares operator by power
+    iteration: ||A||^2 (largest eigenvalue of A A*) for model="adjoint",
+    ||Q||^2 (largest eigenvalue of Q* Q) for model="q"."""
     torch = plan._torch
     gen = torch.Generator(device=plan.device).manual_seed(seed)
     v = torch.randn(plan.volume, dtype=plan.dtype, device=plan.device, generator=gen)
     lam = 0.0
     for _ in range(iters):
         v = v / torch.linalg.vector_norm(v)
-        w = plan.forward(plan.adjoint(v))
+        w = plan.forward(plan.adjoint(v)) if model == "adjoint" else plan.q_adjoint(plan.q(v))
         lam = float(torch.dot(v.reshape(-1), w.reshape(-1)))
         v = w
     return lam
 
 
-def lsq(plan: Plan, g, iters: int = 20, eta: float | None = None, x0=None, callback=None):
-    """Projected gradient descent on J(x) = 1/2 ||A* x - g||^2 with x >= 0.
+def lsq(plan: Plan, g, iters: int = 20, eta: float | None = None, x0=None, callback=None,
+        model: str = "adjoint"):
+    """Projected gradient descent on J(x) = 1/2 ||M x - g||^2 with x >= 0.
 
-    The gradient A (A* x - g) is taken by autograd through NednerAdjoint, so
-    each iteration runs one adjoint and one forward pass of the operator.
-    Returns (x, losses).
+    M is the adjoint A* of the reconstruction (model="adjoint") or the forward
+    operator Q of the wave equation (model="q"). The gradient M* (M x - g) is
+    taken by autograd through NednerAdjoint or NednerQ, so each iteration runs
+    the operator and its transpose once. Returns (x, losses).
     """
     torch = plan._torch
+    if model not in ("adjoint", "q"):
+        raise ValueError("model must be 'adjoint' or 'q'")
     if eta is None:
-        # a step just under 1/L (L = ||A||^2 estimated from below) keeps the
+        # a step just under 1/L (L = ||M||^2 estimated from below) keeps the
         # projected iteration monotone
-        eta = 0.95 / max(power_norm(plan, iters=20), 1e-300)
+        eta = 0.95 / max(power_norm(plan, iters=20, model=model), 1e-300)
+    op = NednerAdjoint if model == "adjoint" else NednerQ
     x = torch.zeros(plan.volume, dtype=plan.dtype, device=plan.device) if x0 is None else x0.clone()
     losses = []
     for it in range(iters):
         x.requires_grad_(True)
-        r = NednerAdjoint.apply(x, plan) - g
+        r = op.apply(x, plan) - g
         loss = 0.5 * torch.sum(r * r)
         (grad,) = torch.autograd.grad(loss, x)
         losses.append(float(loss.detach()))

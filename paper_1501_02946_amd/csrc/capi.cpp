@@ -302,6 +302,7 @@ nedner_status validate_impl(const nedner_desc* d, Derived* out) {
 struct Geometry {
   std::vector<int> cell;        // [M][2]
   std::vector<double> w1, w2;   // [M][W]
+  std::vector<double> w1u;      // [M][W] first-axis window values without s_m
   std::vector<int> ent_m;
   std::vector<double> ent_w2;
   std::vector<int> cellbeg;     // [n2 * nseg][CB]
@@ -329,6 +330,7 @@ void build_geometry(const nedner_desc& d, const Derived& v, Geometry& G) {
   const bool plain = d.prec == NEDNER_FP32_PLAIN;
   G.cell.resize(2 * M);
   G.w1.resize(M * W);
+  G.w1u.resize(M * W);
   G.w2.resize(M * W);
   std::vector<double> frac2(M);
   const double L[2] = {v.L1, v.L2}, a[2] = {d.a1, d.a2};
@@ -365,9 +367,10 @@ void build_geometry(const nedner_desc& d, const Derived& v, Geometry& G) {
         } else {
           w = window_phi(v, double(o) - f);
         }
-        if (ax == 0)
+        if (ax == 0) {
           G.w1[m * W + k] = s * w;
-        else
+          G.w1u[m * W + k] = w;
+        } else
           G.w2[m * W + k] = w;
       }
       if (ax == 1) frac2[m] = f;
@@ -493,6 +496,10 @@ struct nedner_plan_s {
   size_t need_ws = 0;
   size_t off1 = 0;
   std::vector<nedner_plan_s*> subs;  // batched plans
+  // unit sensor weights for the forward operator Q: w1 without s_m, and the
+  // equispaced placement's weights set to one
+  const void* w1_unit = nullptr;
+  const void* s_unit = nullptr;
   // batched plan state (subs non-empty)
   nedner::BatchProb* d_bp = nullptr;       // device problem table
   int2* d_items = nullptr;                 // work lists of all stages, concatenated
@@ -555,7 +562,8 @@ class DeviceGuard {
 
 void destroy_one(nedner_plan p);
 nedner_status batch_upload_table(nedner_plan bp);
-nedner_status forward_impl(nedner_plan plan, const void* d_g, void* d_out, int kind, hipStream_t s);
+nedner_status forward_impl(nedner_plan plan, const void* d_g, void* d_out, int kind, hipStream_t s,
+                           const KP* kp = nullptr);
 nedner_status batch_build_lists(nedner_plan bp);
 size_t stage_blocks(const KP& k, int stage, int cpw);
 size_t pass_lds(const KP& k, int stage);
@@ -703,9 +711,14 @@ nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* ou
   k.w2 = wide ? A.upload(G.w2) : A.upload_as<float>(G.w2);
   k.cell = static_cast<const int*>(A.upload(G.cell));
   k.equi = v.equi;
+  k.cosm = 0;
   if (v.equi) {
     k.node = static_cast<const int*>(A.upload(G.node));
     k.sw = dbl ? A.upload(G.s) : A.upload_as<float>(G.s);
+    const std::vector<double> ones(size_t(desc->m), 1.0);
+    p->s_unit = dbl ? A.upload(ones) : A.upload_as<float>(ones);
+  } else {
+    p->w1_unit = wide ? A.upload(G.w1u) : A.upload_as<float>(G.w1u);
   }
   {
     DevAlloc Lst;
@@ -792,8 +805,10 @@ static const char* kFwdNames = "spread,lat_a,lat_b,column,pass_c,pass_d";
 static const char* kSpecNames = "spread,lat_a,lat_b,column_spectrum";
 static const char* kAdjNames = "adj_d,adj_c,column_adj,adj_b,adj_a,gather";
 
-nedner_status forward_impl(nedner_plan plan, const void* d_g, void* d_out, int kind, hipStream_t s) {
-  const KP& k = plan->kp;
+// kp: launch parameters other than the plan's own (the forward operator Q).
+nedner_status forward_impl(nedner_plan plan, const void* d_g, void* d_out, int kind, hipStream_t s,
+                           const KP* kp) {
+  const KP& k = kp ? *kp : plan->kp;
   char* b0 = static_cast<char*>(plan->ws);
   char* b1 = b0 + plan->off1;
   if (kind == NEDNER_STAGE_GRID) {
@@ -826,8 +841,9 @@ nedner_status forward_impl(nedner_plan plan, const void* d_g, void* d_out, int k
   return NEDNER_OK;
 }
 
-nedner_status adjoint_impl(nedner_plan plan, const void* d_in, int kind, void* d_g, hipStream_t s) {
-  const KP& k = plan->kp;
+nedner_status adjoint_impl(nedner_plan plan, const void* d_in, int kind, void* d_g, hipStream_t s,
+                           const KP* kp = nullptr) {
+  const KP& k = kp ? *kp : plan->kp;
   char* b0 = static_cast<char*>(plan->ws);
   char* b1 = b0 + plan->off1;
   if (kind == NEDNER_STAGE_GRID) {
@@ -852,6 +868,21 @@ nedner_status adjoint_impl(nedner_plan plan, const void* d_in, int kind, void* d
   NEDNER_RUN(k.equi ? nedner::launch_place_adj(k, b0, d_g, s) : nedner::launch_gather(k, b0, d_g, s), "gather");
   NEDNER_RUN(mk.mark(), "event");
   return NEDNER_OK;
+}
+
+// Launch parameters of the forward operator Q of the wave equation (Sec. 2)
+// and of its adjoint: the adjoint and forward pipelines of the plan with unit
+// sensor weights, the constant weight 1/(N1 N2 N3) in place of (dt/d3) W(j,l),
+// and the l, -l average of the NER column values.
+KP trace_params(const nedner_plan p) {
+  KP k = p->kp;
+  if (k.equi)
+    k.sw = p->s_unit;
+  else
+    k.w1 = p->w1_unit;
+  k.scale_vol = 1.0 / (double(k.N1) * double(k.N2) * double(k.N3));
+  k.cosm = 1;
+  return k;
 }
 
 // ---------------------------------------------------------------- batches
@@ -1442,6 +1473,26 @@ nedner_status nedner_execute_adjoint(nedner_plan plan, const void* d_in, int kin
   DeviceGuard guard(plan->device);
   if (!guard.ok()) return fail(NEDNER_E_HIP, "cannot select the plan's device");
   return adjoint_impl(plan, d_in, kind, d_g, static_cast<hipStream_t>(stream));
+}
+
+nedner_status nedner_execute_q(nedner_plan plan, const void* d_v, void* d_g, void* stream) {
+  nedner_status st = exec_check(plan, NEDNER_VOLUME_REAL, true);
+  if (st != NEDNER_OK) return st;
+  if (!d_v || !d_g) return fail(NEDNER_E_ARG, "NULL device pointer");
+  DeviceGuard guard(plan->device);
+  if (!guard.ok()) return fail(NEDNER_E_HIP, "cannot select the plan's device");
+  const KP k = trace_params(plan);
+  return adjoint_impl(plan, d_v, NEDNER_VOLUME_REAL, d_g, static_cast<hipStream_t>(stream), &k);
+}
+
+nedner_status nedner_execute_q_adjoint(nedner_plan plan, const void* d_g, void* d_v, void* stream) {
+  nedner_status st = exec_check(plan, NEDNER_VOLUME_REAL, false);
+  if (st != NEDNER_OK) return st;
+  if (!d_g || !d_v) return fail(NEDNER_E_ARG, "NULL device pointer");
+  DeviceGuard guard(plan->device);
+  if (!guard.ok()) return fail(NEDNER_E_HIP, "cannot select the plan's device");
+  const KP k = trace_params(plan);
+  return forward_impl(plan, d_g, d_v, NEDNER_VOLUME_REAL, static_cast<hipStream_t>(stream), &k);
 }
 
 nedner_status nedner_execute_many(nedner_plan plan, const void* const* d_g, void* const* d_out, int kind,

@@ -14,6 +14,15 @@
 //   FFT along depth is done in LDS, so the column leaves as Z1.
 // Adjoint, per column: the exact transpose, with the interpolation turned
 // into a deterministic gather over the monotone sequence x(l).
+// With p.cosm the same kernels evaluate the forward operator Q of Sec. 2 on
+// the periodic voxel grid (adjoint kernel) and its adjoint (forward kernel):
+// each Fourier mode of the initial pressure oscillates as cos(c|K|t) =
+// (exp(i omega t) + exp(-i omega t))/2, and since x(-l) = -x(l) the second
+// exponential is the first one at -l, so the per-l values are averaged
+// between l and -l and weighted by a constant instead of W(j,l). The depth
+// mode l = 0 oscillates at c|k| (not at the reconstruction's omega = 0), so
+// it is evaluated at the two points +-x0 = +-c dt ntt |k|/(2 pi), which lie
+// between x(-1) and x(1) and keep the sequence of points monotone.
 //
 // Templates only: each precision is instantiated in a translation unit of
 // its own (k_column_f64.hip, k_column_f32.hip, k_column_f32p.hip) so the
@@ -159,6 +168,44 @@ __device__ __forceinline__ LPoint<R, ARGS64> lpoint(const KP& p, double a, int l
   return o;
 }
 
+// Grid position, phase and zero weight of the time frequency at x (grid units).
+template <typename R, bool ARGS64>
+__device__ __forceinline__ LPoint<R, ARGS64> lpoint_at(const KP& p, double x) {
+  LPoint<R, ARGS64> o;
+  R rr;
+  if constexpr (ARGS64) {
+    const double fl = floor(x);
+    o.q0 = int(fl);
+    o.fr = R(x - fl);
+    double r = x * p.phase_p;
+    r -= rint(r);
+    rr = R(r);
+  } else {
+    const float xf = float(x);
+    const float fl = floorf(xf);
+    o.q0 = int(fl);
+    o.fr = R(xf - fl);
+    float r = xf * float(p.phase_p);
+    r -= rintf(r);
+    rr = R(r);
+  }
+  o.wgt = R(0);
+  R s, c;
+  sincos_pi<R>(R(2) * rr, &s, &c);
+  o.ph = cpx<R>{c, -s};
+  return o;
+}
+
+// x0 = c dt ntt |k| / (2 pi) of the lateral mode with squared frequency a,
+// in the precision lpoint uses for x.
+template <bool ARGS64>
+__device__ __forceinline__ double x_lateral(const KP& p, double a) {
+  if constexpr (ARGS64)
+    return p.cdtnt * sqrt(a);
+  else
+    return double(float(p.cdtnt) * sqrtf(float(a)));
+}
+
 // LDS of one workgroup: the two twiddle tables, shared, then per wavefront
 // (one column each) the transform buffer and, unless the forward kernel keeps
 // its per-l values in registers, the per-l arrays.
@@ -167,9 +214,9 @@ struct ColSmem {
   cpx<R>* twt;  // ntt twiddles
   cpx<R>* tw3;  // N3 twiddles
   cpx<R>* a;    // nbuf: the transform buffer (in place)
-  cpx<R>* fl;   // N3 + 1
-  R* fr;        // N3 + 1 (adjoint)
-  int* q0;      // N3 + 1 (adjoint)
+  cpx<R>* fl;   // N3 + 2: one value per output l, and the second l = 0 point of Q
+  R* fr;        // N3 + 2 (adjoint)
+  int* q0;      // N3 + 2 (adjoint)
 };
 
 // The forward kernel holds the N3 + 1 values of a column in registers, NL_REG
@@ -183,7 +230,7 @@ __host__ __device__ inline size_t col_wave_bytes(int ntt, int N3, bool adj) {
   const size_t nbuf = (ntt > N3 ? ntt : N3) + COL_EXT;
   size_t b = sizeof(cpx<R>) * nbuf;
   if (adj || !col_fl_in_regs(N3))
-    b += sizeof(cpx<R>) * ((size_t)N3 + 1) + (sizeof(R) + sizeof(int)) * ((size_t)N3 + 1);
+    b += (sizeof(cpx<R>) + sizeof(R) + sizeof(int)) * ((size_t)N3 + 2);
   return (b + 15) & ~size_t(15);
 }
 
@@ -201,8 +248,8 @@ __device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int wav
   char* w = smem + col_shared_bytes<R>(p.ntt, p.N3) + (size_t)wave * col_wave_bytes<R>(p.ntt, p.N3, adj);
   s.a = reinterpret_cast<cpx<R>*>(w);
   s.fl = s.a + nbuf;
-  s.fr = reinterpret_cast<R*>(s.fl + p.N3 + 1);
-  s.q0 = reinterpret_cast<int*>(s.fr + p.N3 + 1);
+  s.fr = reinterpret_cast<R*>(s.fl + p.N3 + 2);
+  s.q0 = reinterpret_cast<int*>(s.fr + p.N3 + 2);
   return s;
 }
 
@@ -246,6 +293,8 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
   const int j1 = je - p.N1 / 2;
   const double a = double(j1) * double(j1) * p.inv_L1sq + double(k2) * double(k2) * p.inv_L2sq;
   const double scale = SPEC ? p.scale_spec : p.scale_vol;
+  const bool cosm = !SPEC && p.cosm != 0;
+  const R cscale = R(scale);
   const R beta = R(p.beta);
   // Ratios of neighbouring window values: with d = o - fr,
   //   phi(o+1-fr) / phi(o-fr) = exp(-beta (2o+1)) exp(2 beta fr),
@@ -259,9 +308,8 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
   // the value of output li = lane + 64 i, i < NL_REG, when they stay in registers
   cpx<R> hl[NL_REG];
   const bool in_regs = col_fl_in_regs(N3);
-  auto gather = [&](int li) {
-    const int l = li - h3;
-    const LPoint<R, ARGS64> lp = lpoint<R, ARGS64>(p, a, l, scale);
+  // H(x) exp(-i phase) at the point lp
+  auto taps = [&](const LPoint<R, ARGS64>& lp) {
     // taps q0 - W/2 + 1 .. q0 + W/2 read from b .. b + W - 1 (no wrap)
     const cpx<R>* Bq = B + pmodc(lp.q0 - W / 2 + 1, ntt) + (W / 2 - 1);
     cpx<R> H;
@@ -295,7 +343,11 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
         H = H + Bq[o] * wexp<R>(-beta * d * d);
       }
     }
-    return cmul(H, lp.ph) * lp.wgt;
+    return cmul(H, lp.ph);
+  };
+  auto gather = [&](int li) {
+    const LPoint<R, ARGS64> lp = lpoint<R, ARGS64>(p, a, li - h3, scale);
+    return taps(lp) * (cosm ? cscale : lp.wgt);
   };
   if (in_regs) {
 #pragma unroll
@@ -305,6 +357,12 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
     }
   } else {
     for (int li = lane; li <= N3; li += 64) sm.fl[li] = gather(li);
+  }
+  // Q*: the l = 0 value from the two points +-x0
+  cpx<R> hz = {R(0), R(0)};
+  if (cosm && lane == 0) {
+    const double x0 = x_lateral<ARGS64>(p, a);
+    hz = (taps(lpoint_at<R, ARGS64>(p, x0)) + taps(lpoint_at<R, ARGS64>(p, -x0))) * (R(0.5) * cscale);
   }
   wave_sync();
   if constexpr (SPEC) {
@@ -349,6 +407,22 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
       for (int li = lane; li <= N3; li += 64) place(li, sm.fl[li]);
     }
     wave_sync();
+    if (cosm) {
+      // average slot s (l) with slot N3 - s (-l); the Nyquist pair is h3, N3;
+      // slot 0 (l = 0) takes the two-point value
+      if (lane == 0) X[0] = hz * f;
+      for (int s = lane + 1; s < h3; s += 64) {
+        const cpx<R> m = (X[s] + X[N3 - s]) * R(0.5);
+        X[s] = m;
+        X[N3 - s] = m;
+      }
+      if (lane == 0) {
+        const cpx<R> m = (X[h3] + X[N3]) * R(0.5);
+        X[h3] = m;
+        X[N3] = m;
+      }
+      wave_sync();
+    }
     if (lane == 0) {
       const cpx<R> lo = X[h3], hi = X[N3];
       X[h3] = pol == 0 ? lo : (pol == 1 ? hi : (lo + hi) * R(0.5));
@@ -412,19 +486,40 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
   const R f = R(fac);
   const R mlo = pol == 0 ? R(1) : (pol == 1 ? R(0) : R(0.5));
   const R mhi = pol == 1 ? R(1) : (pol == 0 ? R(0) : R(0.5));
-  for (int li = lane; li <= N3; li += 64) {
-    const int l = li - h3;
-    cpx<R> fp;
-    if (li == 0)
-      fp = Xp[h3] * (f * mlo);
-    else if (li == N3)
-      fp = Xp[h3] * (f * mhi);
-    else
-      fp = Xp[pmodc(l, N3)] * f;
-    const LPoint<R, ARGS64> lp = lpoint<R, ARGS64>(p, a, l, p.scale_vol);
-    sm.fl[li] = cmulc(fp, lp.ph) * lp.wgt;  // H'(l) = wgt * conj(ph) * F'(l)
-    sm.q0[li] = lp.q0;
-    sm.fr[li] = lp.fr;
+  const bool cosm = p.cosm != 0;
+  // F'(l) of output li: the Nyquist representatives share Xp[h3] by the policy
+  auto fprime = [&](int li) {
+    if (li == 0) return Xp[h3] * (f * mlo);
+    if (li == N3) return Xp[h3] * (f * mhi);
+    return Xp[pmodc(li - h3, N3)] * f;
+  };
+  // points e: output li = e; with cosm the l = 0 output is the pair of points
+  // e = h3 (-x0) and h3 + 1 (+x0), and li = e - 1 above them
+  const int npt = N3 + 1 + (cosm ? 1 : 0);
+  const double x0 = cosm ? x_lateral<ARGS64>(p, a) : 0.0;
+  for (int e = lane; e < npt; e += 64) {
+    int li = e, side = 0;
+    if (cosm && e >= h3) {
+      if (e == h3)
+        side = -1;
+      else if (e == h3 + 1)
+        li = h3, side = 1;
+      else
+        li = e - 1;
+    }
+    cpx<R> fp = fprime(li);
+    LPoint<R, ARGS64> lp;
+    if (cosm) {
+      fp = (fp + fprime(N3 - li)) * R(0.5);  // transpose of the l, -l average
+      lp = side ? lpoint_at<R, ARGS64>(p, side * x0) : lpoint<R, ARGS64>(p, a, li - h3, p.scale_vol);
+      if (side) fp = fp * R(0.5);
+      lp.wgt = R(p.scale_vol);
+    } else {
+      lp = lpoint<R, ARGS64>(p, a, li - h3, p.scale_vol);
+    }
+    sm.fl[e] = cmulc(fp, lp.ph) * lp.wgt;  // H'(l) = wgt * conj(ph) * F'(l)
+    sm.q0[e] = lp.q0;
+    sm.fr[e] = lp.fr;
   }
   wave_sync();
   // B'[q] = sum over l whose taps cover q of phi(x_l - q) H'(l); x_l is
@@ -438,8 +533,8 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
     for (int m = -mwrap; m <= mwrap; ++m) {
       const int qv = qc + m * ntt;
       // tap o = qv - q0 must lie in [-W/2+1, W/2]: q0 in [qv - W/2, qv + W/2 - 1]
-      const int lo = lower_bound_i(sm.q0, 0, N3 + 1, qv - W / 2);
-      const int hi = lower_bound_i(sm.q0, lo, N3 + 1, qv + W / 2);
+      const int lo = lower_bound_i(sm.q0, 0, npt, qv - W / 2);
+      const int hi = lower_bound_i(sm.q0, lo, npt, qv + W / 2);
       for (int li = lo; li < hi; ++li) {
         const R d = R(qv - sm.q0[li]) - sm.fr[li];
         if constexpr (KBW)

@@ -36,6 +36,9 @@ struct KP {
   int pass_ip;    // FFT passes: in-place (1) or ping-pong (0) transform
   int window;     // 0: Gaussian exp(-beta x^2); 1: Kaiser-Bessel I0(beta sqrt(1 - (2x/W)^2))
   int equi;       // sensors on the output grid: placement instead of spreading, n1 = N1, n2 = N2
+  int cosm;       // forward operator Q of the wave equation and its adjoint: the NER column
+                  // values are averaged between l and -l (the cosine of the standing wave)
+                  // and weighted by the constant scale_vol instead of W(j,l)
 
   // ---- window and frequency constants (double, reduced on the host) -----
   double beta;      // window parameter (see window), x in grid units, all three axes

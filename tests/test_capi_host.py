@@ -157,6 +157,8 @@ def test_calls_without_plan_fail_cleanly():
     L = N.lib()
     assert L.nedner_execute(None, None, None, 0, None) == E_ARG
     assert L.nedner_execute_adjoint(None, None, 0, None, None) == E_ARG
+    assert L.nedner_execute_q(None, None, None, None) == E_ARG
+    assert L.nedner_execute_q_adjoint(None, None, None, None) == E_ARG
     assert L.nedner_set_workspace(None, None, 0) == E_ARG
     sz = ctypes.c_size_t(0)
     assert L.nedner_workspace_size(None, ctypes.byref(sz)) == E_ARG
