@@ -51,7 +51,7 @@ __all__ = ["Geometry", "geometry", "mode_numbers", "wavenumbers", "omega",
            "weight", "ned", "ner", "spectrum", "volume_from_spectrum",
            "forward", "adjoint", "brute_spectrum", "brute_volume",
            "brute_matrix", "spectrum_at", "trace", "trace_adjoint",
-           "brute_trace"]
+           "brute_trace", "corrcoef", "tenenbaum", "mip"]
 
 # Memory cap for one block of the exponential matrix (complex128 entries).
 _BLOCK_ENTRIES = 1 << 24
@@ -420,3 +420,52 @@ def brute_trace(v, xy, geo: Geometry) -> np.ndarray:
                         t = geo.t0 + n * geo.dt
                         out[mm, n] += (coef * math.cos(geo.c * kk * t) * lat).real
     return out
+
+
+# --------------------------------------------------------------------------
+# Image quality measures of App. B and maximum intensity projections.
+# --------------------------------------------------------------------------
+
+def corrcoef(a, b, mask=None) -> float:
+    """Correlation coefficient of two images (App. B, eq. (11)):
+    Cov(a, b) / sqrt(Var(a) Var(b)) over the elements where mask is true
+    (all elements without a mask), with population moments in float64.
+    """
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    if mask is not None:
+        keep = np.asarray(mask).ravel().astype(bool)
+        a, b = a[keep], b[keep]
+    da = a - a.mean()
+    db = b - b.mean()
+    return float(np.sum(da * db) / math.sqrt(np.sum(da * da) * np.sum(db * db)))
+
+
+def tenenbaum(img, rect=None) -> float:
+    """Tenenbaum sharpness of a 2-D image (App. B, eqs. (12)-(13)): the sum
+    over pixels of (g * U)^2 + (g^T * U)^2 with g the 3x3 Sobel kernel
+    [[-1, 0, 1], [-2, 0, 2], [-1, 0, 1]].
+
+    The sum runs over the pixels (r, c) of rect = (r0, r1, c0, c1) (half-open;
+    the whole image without it) whose 3x3 neighbourhood lies inside the image.
+    Each pixel's two responses are summed term by term.
+    """
+    u = np.asarray(img, dtype=np.float64)
+    rows, cols = u.shape
+    r0, r1, c0, c1 = (0, rows, 0, cols) if rect is None else rect
+    r0, c0 = max(r0, 1), max(c0, 1)
+    r1, c1 = min(r1, rows - 1), min(c1, cols - 1)
+    g = np.array([[-1.0, 0.0, 1.0], [-2.0, 0.0, 2.0], [-1.0, 0.0, 1.0]])
+    total = 0.0
+    for r in range(r0, r1):
+        for c in range(c0, c1):
+            patch = u[r - 1:r + 2, c - 1:c + 2]
+            gx = float(np.sum(g * patch))
+            gy = float(np.sum(g.T * patch))
+            total += gx * gx + gy * gy
+    return total
+
+
+def mip(vol, axis: int) -> np.ndarray:
+    """Maximum intensity projection of a volume along `axis`."""
+    return np.max(np.asarray(vol), axis=axis)
