@@ -11,6 +11,9 @@ resident batch of synthetic sensor data. Prints ONE JSON line:
   cpu_baseline the FP64 oracle timed on the host on the same workload
   fp64_plain   the same operator in FP64 on the GPU, and the FP32 speedup
   kaiser_bessel_w8  the same workload with the Kaiser-Bessel window at 8 taps
+  adjoint      the exact adjoint A* (volume -> data) on the same plan, per stage
+  image_measures    the App. B measures of the reconstruction: correlation with
+               the rasterised phantom, Tenenbaum sharpness of the depth MIP
   forward_model_q   the forward operator Q of the wave equation (volume -> data)
                and its adjoint on the same plan, per-stage times, and sampled
                outputs of Q against the oracle
@@ -307,6 +310,8 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-kb", action="store_true",
                     help="skip the Kaiser-Bessel (8-tap) leg timed beside the headline")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the leg timing the exact adjoint")
     ap.add_argument("--no-q", action="store_true",
                     help="skip the leg timing the forward operator Q and its adjoint")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -416,6 +421,21 @@ def main(argv=None):
                                        stages_ms={k: round(v, 5) for k, v in stkb.items()})
         volkb = okb.cpu().numpy()
         del pkb
+    if not a.no_adjoint:
+        # the exact adjoint (a transpose pass of every stage) on the reconstructed volume
+        da = torch.empty((p.m, p.nt), dtype=plan.dtype, device=plan.device)
+        msa, _ = time_op(torch, plan, lambda: plan.adjoint(out, out=da), a.steps, a.warmup)
+        _, sta = time_op(torch, plan, lambda: plan.adjoint(out, out=da), a.steps, 1, profile=True)
+        res["adjoint"] = dict(ms_per_step=round(msa, 5), value=round(points / (msa / 1e3) / 1e6, 2),
+                              unit="Mpts/s", stages_ms={k: round(v, 5) for k, v in sta.items()})
+        del da
+    # image measures of App. B on the reconstruction (GPU kernels)
+    phantom = torch.as_tensor(synth.phantom_volume(p), dtype=plan.dtype, device=plan.device)
+    msm, _ = time_op(torch, plan, lambda: N.mip(out, 2), a.steps, a.warmup)
+    res["image_measures"] = dict(corrcoef_vs_phantom=round(N.corrcoef(out, phantom), 6),
+                                 tenenbaum_depth_mip=N.tenenbaum(N.mip(out, 2)),
+                                 mip_ms=round(msm, 5))
+    del phantom
     qsample = None
     if not a.no_q:
         # the forward operator Q (initial pressure -> sensor traces) on the

@@ -78,6 +78,12 @@ typedef enum {
   NEDNER_FP32_PLAIN = 3         /* float everywhere, arguments included */
 } nedner_precision;
 
+/* Element type of the image measures' inputs. */
+typedef enum {
+  NEDNER_DTYPE_F32 = 0,
+  NEDNER_DTYPE_F64 = 1
+} nedner_dtype;
+
 /* Interpolation window of the spreading (eq. (10)) and of the NER gather
    (eq. (8)), the same on all three axes, W taps per axis around each point.
    Gaussian: phi(x) = exp(-beta x^2), beta = pi (sigma - 1/2) / (sigma W/2) / tau_scale
@@ -223,6 +229,37 @@ nedner_status nedner_execute_many(nedner_plan plan, const void* const* d_g,
                                   void* const* d_out, int kind, void* stream);
 
 nedner_status nedner_destroy(nedner_plan plan);
+
+/* ---- image measures (App. B) and projections: no plan needed ----------- */
+
+/* Device workspace (bytes) of nedner_corrcoef and nedner_tenenbaum. */
+size_t nedner_metrics_workspace_size(void);
+
+/* Maximum intensity projection of a device volume (n1, n2, n3), depth
+   fastest, along `axis` (0, 1 or 2) into d_out: (n2, n3), (n1, n3) or
+   (n1, n2), row-major, same dtype. Inputs are assumed finite. */
+nedner_status nedner_mip(const void* d_vol, int n1, int n2, int n3, int axis, int dtype, void* d_out,
+                         void* stream);
+
+/* Correlation coefficient of two device arrays of n elements (App. B,
+   eq. (11)): Cov(a, b) / sqrt(Var(a) Var(b)) over the elements whose mask
+   byte is non-zero (all elements when d_mask is NULL), in two passes (means,
+   then centred sums) accumulated in double. The result goes to the device
+   double *d_result (NaN when a variance is zero or no element is selected).
+   d_work: device workspace of nedner_metrics_workspace_size() bytes, not
+   shared with a concurrent call. Deterministic. */
+nedner_status nedner_corrcoef(const void* d_a, const void* d_b, const unsigned char* d_mask, int64_t n,
+                              int dtype, double* d_result, void* d_work, size_t work_bytes, void* stream);
+
+/* Tenenbaum sharpness of a device image (rows, cols), row-major (App. B,
+   eqs. (12)-(13)): the sum of (g * U)^2 + (g^T * U)^2, g the 3x3 Sobel kernel
+   [[-1, 0, 1], [-2, 0, 2], [-1, 0, 1]], over the pixels of the half-open
+   rectangle [r0, r1) x [c0, c1) whose 3x3 neighbourhood lies inside the
+   image; accumulated in double into *d_result. Same workspace rules as
+   nedner_corrcoef. */
+nedner_status nedner_tenenbaum(const void* d_img, int64_t rows, int64_t cols, int64_t r0, int64_t r1,
+                               int64_t c0, int64_t c1, int dtype, double* d_result, void* d_work,
+                               size_t work_bytes, void* stream);
 
 /* Current launch shape of a plan (of its first problem for a batch). */
 nedner_status nedner_get_tuning(nedner_plan plan, nedner_tuning* tuning);

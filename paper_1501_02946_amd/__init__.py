@@ -20,6 +20,7 @@ import os
 import numpy as np
 
 __all__ = ["Plan", "BatchPlan", "NednerRecon", "NednerAdjoint", "NednerQ", "NednerError", "lib", "lsq",
+           "mip", "corrcoef", "tenenbaum",
            "power_norm", "PRECISIONS", "KINDS", "FLAGS", "desc_struct", "info_struct",
            "query"]
 
@@ -77,7 +78,9 @@ EXPORTS = ["nedner_desc_init", "nedner_validate", "nedner_query", "nedner_plan_c
            "nedner_set_workspace", "nedner_execute", "nedner_execute_adjoint",
            "nedner_execute_many", "nedner_destroy", "nedner_status_string",
            "nedner_last_error", "nedner_version", "nedner_profile_begin", "nedner_profile_end",
-           "nedner_get_tuning", "nedner_set_tuning", "nedner_autotune"]
+           "nedner_get_tuning", "nedner_set_tuning", "nedner_autotune", "nedner_execute_q",
+           "nedner_execute_q_adjoint", "nedner_metrics_workspace_size", "nedner_mip",
+           "nedner_corrcoef", "nedner_tenenbaum"]
 
 
 def _declare(L):
@@ -96,6 +99,12 @@ def _declare(L):
     L.nedner_execute_adjoint.argtypes = [vp, vp, i32, vp, vp]
     L.nedner_execute_many.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
     L.nedner_execute_q.argtypes = [vp, vp, vp, vp]
+    i64 = ctypes.c_int64
+    L.nedner_metrics_workspace_size.argtypes = []
+    L.nedner_metrics_workspace_size.restype = sz
+    L.nedner_mip.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
+    L.nedner_corrcoef.argtypes = [vp, vp, vp, i64, i32, vp, vp, sz, vp]
+    L.nedner_tenenbaum.argtypes = [vp, i64, i64, i64, i64, i64, i64, i32, vp, vp, sz, vp]
     L.nedner_execute_q_adjoint.argtypes = [vp, vp, vp, vp]
     L.nedner_destroy.argtypes = [vp]
     L.nedner_status_string.argtypes = [i32]
@@ -111,7 +120,8 @@ def _declare(L):
     L.nedner_set_tuning.argtypes = [vp, T]
     L.nedner_autotune.argtypes = [vp, vp, vp, T]
     for name in EXPORTS:
-        if name not in ("nedner_desc_init", "nedner_status_string", "nedner_last_error"):
+        if name not in ("nedner_desc_init", "nedner_status_string", "nedner_last_error",
+                        "nedner_metrics_workspace_size"):
             getattr(L, name).restype = ctypes.c_int
 
 
@@ -586,3 +596,76 @@ def lsq(plan: Plan, g, iters: int = 20, eta: float | None = None, x0=None, callb
         if callback is not None:
             callback(it, x, losses[-1])
     return x.detach(), losses
+
+
+# ---------------------------------------------------------------- image measures
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return 0
+    if t.dtype == torch.float64:
+        return 1
+    raise ValueError("float32 or float64 tensors only")
+
+
+def _metric_buffers(t):
+    import torch
+    work = torch.empty(int(lib().nedner_metrics_workspace_size()), dtype=torch.uint8, device=t.device)
+    res = torch.empty(1, dtype=torch.float64, device=t.device)
+    return work, res
+
+
+def mip(vol, axis: int):
+    """Maximum intensity projection of a device volume (N1, N2, N3) along `axis`."""
+    import torch
+    if vol.dim() != 3 or not vol.is_cuda:
+        raise ValueError("a 3-D device tensor is expected")
+    v = vol.contiguous()
+    shape = [s for k, s in enumerate(v.shape) if k != axis]
+    out = torch.empty(shape, dtype=v.dtype, device=v.device)
+    with torch.cuda.device(v.device):
+        _check(lib().nedner_mip(ctypes.c_void_p(v.data_ptr()), v.shape[0], v.shape[1], v.shape[2], int(axis),
+                                _dtype_code(v), ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(torch.cuda.current_stream(v.device).cuda_stream)))
+    return out
+
+
+def corrcoef(a, b, mask=None) -> float:
+    """Correlation coefficient of two device arrays of equal shape (App. B,
+    eq. (11)), over the elements where `mask` (bool tensor) is true."""
+    import torch
+    if a.shape != b.shape or a.dtype != b.dtype or not a.is_cuda:
+        raise ValueError("two device tensors of one shape and dtype are expected")
+    x, y = a.contiguous(), b.contiguous()
+    m = None
+    if mask is not None:
+        if mask.shape != a.shape:
+            raise ValueError("mask shape differs")
+        m = mask.to(device=a.device, dtype=torch.uint8).contiguous()
+    work, res = _metric_buffers(x)
+    with torch.cuda.device(x.device):
+        _check(lib().nedner_corrcoef(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                     ctypes.c_void_p(m.data_ptr() if m is not None else 0), x.numel(),
+                                     _dtype_code(x), ctypes.c_void_p(res.data_ptr()),
+                                     ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                     ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)))
+    return float(res.item())
+
+
+def tenenbaum(img, rect=None) -> float:
+    """Tenenbaum sharpness of a device image (rows, cols) (App. B, eqs. (12)-(13))
+    over the pixels of rect = (r0, r1, c0, c1) with a full 3x3 neighbourhood."""
+    import torch
+    if img.dim() != 2 or not img.is_cuda:
+        raise ValueError("a 2-D device tensor is expected")
+    u = img.contiguous()
+    rows, cols = u.shape
+    r0, r1, c0, c1 = (0, rows, 0, cols) if rect is None else rect
+    work, res = _metric_buffers(u)
+    with torch.cuda.device(u.device):
+        _check(lib().nedner_tenenbaum(ctypes.c_void_p(u.data_ptr()), rows, cols, r0, r1, c0, c1,
+                                      _dtype_code(u), ctypes.c_void_p(res.data_ptr()),
+                                      ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                      ctypes.c_void_p(torch.cuda.current_stream(u.device).cuda_stream)))
+    return float(res.item())

@@ -1590,6 +1590,47 @@ nedner_status nedner_autotune(nedner_plan plan, const void* d_g, void* stream, n
   return plan->subs.empty() ? autotune_single(plan, d_g, s, best) : autotune_batch(plan, s, best);
 }
 
+size_t nedner_metrics_workspace_size(void) { return nedner::METRICS_WORK_BYTES; }
+
+nedner_status nedner_mip(const void* d_vol, int n1, int n2, int n3, int axis, int dtype, void* d_out,
+                         void* stream) {
+  if (!d_vol || !d_out) return fail(NEDNER_E_ARG, "NULL device pointer");
+  if (n1 < 1 || n2 < 1 || n3 < 1) return fail(NEDNER_E_ARG, "volume sizes must be positive");
+  if (axis < 0 || axis > 2) return fail(NEDNER_E_ARG, "axis must be 0, 1 or 2");
+  if (dtype != NEDNER_DTYPE_F32 && dtype != NEDNER_DTYPE_F64) return fail(NEDNER_E_ARG, "unknown dtype");
+  const hipError_t e = nedner::launch_mip(d_vol, n1, n2, n3, axis, dtype == NEDNER_DTYPE_F64, d_out,
+                                          static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NEDNER_OK : fail(NEDNER_E_HIP, std::string("mip: ") + hipGetErrorString(e));
+}
+
+nedner_status nedner_corrcoef(const void* d_a, const void* d_b, const unsigned char* d_mask, int64_t n,
+                              int dtype, double* d_result, void* d_work, size_t work_bytes, void* stream) {
+  if (!d_a || !d_b || !d_result || !d_work) return fail(NEDNER_E_ARG, "NULL device pointer");
+  if (n < 1) return fail(NEDNER_E_ARG, "n must be positive");
+  if (dtype != NEDNER_DTYPE_F32 && dtype != NEDNER_DTYPE_F64) return fail(NEDNER_E_ARG, "unknown dtype");
+  if (work_bytes < nedner::METRICS_WORK_BYTES)
+    return fail(NEDNER_E_WORKSPACE, "workspace smaller than nedner_metrics_workspace_size");
+  const hipError_t e = nedner::launch_corrcoef(d_a, d_b, d_mask, long(n), dtype == NEDNER_DTYPE_F64, d_result,
+                                               d_work, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NEDNER_OK : fail(NEDNER_E_HIP, std::string("corrcoef: ") + hipGetErrorString(e));
+}
+
+nedner_status nedner_tenenbaum(const void* d_img, int64_t rows, int64_t cols, int64_t r0, int64_t r1,
+                               int64_t c0, int64_t c1, int dtype, double* d_result, void* d_work,
+                               size_t work_bytes, void* stream) {
+  if (!d_img || !d_result || !d_work) return fail(NEDNER_E_ARG, "NULL device pointer");
+  if (rows < 1 || cols < 1) return fail(NEDNER_E_ARG, "image sizes must be positive");
+  if (r0 < 0 || c0 < 0 || r1 > rows || c1 > cols || r0 > r1 || c0 > c1)
+    return fail(NEDNER_E_ARG, "rectangle outside the image");
+  if (dtype != NEDNER_DTYPE_F32 && dtype != NEDNER_DTYPE_F64) return fail(NEDNER_E_ARG, "unknown dtype");
+  if (work_bytes < nedner::METRICS_WORK_BYTES)
+    return fail(NEDNER_E_WORKSPACE, "workspace smaller than nedner_metrics_workspace_size");
+  const hipError_t e = nedner::launch_tenenbaum(d_img, long(rows), long(cols), long(r0), long(r1), long(c0),
+                                                long(c1), dtype == NEDNER_DTYPE_F64, d_result, d_work,
+                                                static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NEDNER_OK : fail(NEDNER_E_HIP, std::string("tenenbaum: ") + hipGetErrorString(e));
+}
+
 nedner_status nedner_destroy(nedner_plan plan) {
   destroy_one(plan);
   return NEDNER_OK;

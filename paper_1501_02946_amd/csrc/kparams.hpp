@@ -112,6 +112,15 @@ hipError_t launch_place(const KP& p, const void* g, void* U, hipStream_t s);
 hipError_t launch_place_adj(const KP& p, const void* U, void* g, hipStream_t s);
 // Workgroups of the forward spreading kernel (prec, W, TT, spread_pd, wide_w of p) per CU.
 int spread_blocks_per_cu(const KP& p);
+
+// Image measures and projections (k_metrics.hip); the reductions use a
+// caller workspace of METRICS_WORK_BYTES.
+constexpr size_t METRICS_WORK_BYTES = 16384;
+hipError_t launch_mip(const void* vol, int n1, int n2, int n3, int axis, bool dbl, void* out, hipStream_t s);
+hipError_t launch_corrcoef(const void* a, const void* b, const unsigned char* mask, long n, bool dbl,
+                           double* result, void* work, hipStream_t s);
+hipError_t launch_tenenbaum(const void* img, long rows, long cols, long r0, long r1, long c0, long c1, bool dbl,
+                            double* result, void* work, hipStream_t s);
 hipError_t launch_gather(const KP& p, const void* U, void* g, hipStream_t s);
 hipError_t launch_lat_a(const KP& p, const void* U, void* V, hipStream_t s);
 hipError_t launch_lat_b(const KP& p, const void* V, void* G, hipStream_t s);

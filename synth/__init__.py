@@ -84,6 +84,24 @@ class Problem:
                     a2=self.a2, d1=self.d1, d2=self.d2, d3=self.d3)
 
 
+def phantom_volume(p: "Problem") -> np.ndarray:
+    """The problem's balls sampled on its voxel grid: voxel (i1, i2, i3) at
+    (a1 + i1 d1, a2 + i2 d2, i3 d3) takes the sum of p0 over the balls that
+    contain it (d1, d2 default to 1/n, d3 to c nt dt / n3, as in the plans)."""
+    d1 = p.d1 or 1.0 / p.n1
+    d2 = p.d2 or 1.0 / p.n2
+    d3 = p.d3 or p.c * p.nt * p.dt / p.n3
+    x1 = p.a1 + d1 * np.arange(p.n1)
+    x2 = p.a2 + d2 * np.arange(p.n2)
+    z = d3 * np.arange(p.n3)
+    out = np.zeros((p.n1, p.n2, p.n3))
+    for (bx, by, bz, R, p0) in p.balls:
+        r2 = ((x1[:, None, None] - bx) ** 2 + (x2[None, :, None] - by) ** 2
+              + (z[None, None, :] - bz) ** 2)
+        out += np.where(r2 <= R * R, p0, 0.0)
+    return out
+
+
 def five_smooth_at_least(n: int, even: bool = False) -> int:
     """Smallest integer >= n whose prime factors are all in {2, 3, 5} (even if asked)."""
     k = max(1, int(n))

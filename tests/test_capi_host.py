@@ -159,6 +159,10 @@ def test_calls_without_plan_fail_cleanly():
     assert L.nedner_execute_adjoint(None, None, 0, None, None) == E_ARG
     assert L.nedner_execute_q(None, None, None, None) == E_ARG
     assert L.nedner_execute_q_adjoint(None, None, None, None) == E_ARG
+    assert L.nedner_mip(None, 2, 2, 2, 0, 0, None, None) == E_ARG
+    assert L.nedner_corrcoef(None, None, None, 4, 0, None, None, 0, None) == E_ARG
+    assert L.nedner_tenenbaum(None, 4, 4, 0, 4, 0, 4, 0, None, None, 0, None) == E_ARG
+    assert L.nedner_metrics_workspace_size() >= 8 * (3 * 512 + 2)
     assert L.nedner_set_workspace(None, None, 0) == E_ARG
     sz = ctypes.c_size_t(0)
     assert L.nedner_workspace_size(None, ctypes.byref(sz)) == E_ARG
