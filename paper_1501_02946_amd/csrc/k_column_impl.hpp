@@ -527,11 +527,15 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
   cpx<R>* Bp = sm.a;
   const R beta = R(p.beta);
   const R twow = R(2.0 / W);
+  // the points' grid cells span [qlo, qhi]; an image of the time grid whose
+  // tap window misses that span has no contribution
+  const int qlo = sm.q0[0], qhi = sm.q0[npt - 1];
   for (int q = lane; q < ntt; q += 64) {
     const int qc = q < ntt / 2 ? q : q - ntt;
     cpx<R> acc = {R(0), R(0)};
     for (int m = -mwrap; m <= mwrap; ++m) {
       const int qv = qc + m * ntt;
+      if (qv + W / 2 - 1 < qlo || qv - W / 2 > qhi) continue;
       // tap o = qv - q0 must lie in [-W/2+1, W/2]: q0 in [qv - W/2, qv + W/2 - 1]
       const int lo = lower_bound_i(sm.q0, 0, npt, qv - W / 2);
       const int hi = lower_bound_i(sm.q0, lo, npt, qv + W / 2);

@@ -374,12 +374,20 @@ __global__ __launch_bounds__(256) void k_spread(KP p, const int* __restrict__ ce
 // One wavefront per sensor and time chunk; the W x W taps are read straight
 // from the grid (coalesced along time) and summed in a fixed order.
 template <int W, int TT, typename R, typename WT, typename A>
-__device__ __forceinline__ void gather_body(const KP& p, int bx, int by, const R* __restrict__ U,
+__device__ __forceinline__ void gather_body(const KP& p, int bx, const R* __restrict__ U,
                                             R* __restrict__ g, int vec) {
   const int lane = threadIdx.x & 63;
-  const int m = __builtin_amdgcn_readfirstlane(bx * 4 + (int)(threadIdx.x >> 6));
+  // XCD-aware order: each of the 8 XCDs takes a contiguous run of sensor
+  // groups of one time chunk, so that neighbouring sensors, which read mostly
+  // the same grid rows, share its L2
+  const int ngrp = (p.M + 3) / 4;
+  const int G = ngrp * p.nchunk;
+  const int per = (G + 7) / 8;
+  const int L = (bx & 7) * per + (bx >> 3);
+  if (L >= G) return;
+  const int chunk = L / ngrp;
+  const int m = __builtin_amdgcn_readfirstlane((L - chunk * ngrp) * 4 + (int)(threadIdx.x >> 6));
   if (m >= p.M) return;
-  const int chunk = by;
   const int Nt = p.Nt;
   const int tb = chunk * 64 * TT + lane * TT;
   const int valid = Nt - tb;
@@ -418,7 +426,7 @@ __device__ __forceinline__ void gather_body(const KP& p, int bx, int by, const R
 template <int W, int TT, typename R, typename WT, typename A>
 __global__ __launch_bounds__(256) void k_gather(KP p, const R* __restrict__ U, R* __restrict__ g,
                                                 int vec) {
-  gather_body<W, TT, R, WT, A>(p, blockIdx.x, blockIdx.y, U, g, vec);
+  gather_body<W, TT, R, WT, A>(p, blockIdx.x, U, g, vec);
 }
 
 // ---------------------------------------------------------------------------
@@ -447,7 +455,8 @@ static hipError_t spread_wt(const KP& p, const void* g, void* U, int vec, hipStr
 
 template <typename R, typename WT, typename A, int W, int TT>
 static hipError_t gather_wt(const KP& p, const void* U, void* g, int vec, hipStream_t s) {
-  dim3 grid((p.M + 3) / 4, p.nchunk);
+  const long G = (long)((p.M + 3) / 4) * p.nchunk;
+  dim3 grid(unsigned(8 * ((G + 7) / 8)));
   hipLaunchKernelGGL((k_gather<W, TT, R, WT, A>), grid, dim3(256), 0, s,
                      p, static_cast<const R*>(U), static_cast<R*>(g), vec);
   return hipGetLastError();
