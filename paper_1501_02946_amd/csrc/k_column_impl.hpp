@@ -217,6 +217,7 @@ struct ColSmem {
   cpx<R>* fl;   // N3 + 2: one value per output l, and the second l = 0 point of Q
   R* fr;        // N3 + 2 (adjoint)
   int* q0;      // N3 + 2 (adjoint)
+  int* st;      // ntt + 2 (adjoint): number of points below each grid cell
 };
 
 // The forward kernel holds the N3 + 1 values of a column in registers, NL_REG
@@ -231,6 +232,7 @@ __host__ __device__ inline size_t col_wave_bytes(int ntt, int N3, bool adj) {
   size_t b = sizeof(cpx<R>) * nbuf;
   if (adj || !col_fl_in_regs(N3))
     b += (sizeof(cpx<R>) + sizeof(R) + sizeof(int)) * ((size_t)N3 + 2);
+  if (adj) b += sizeof(int) * ((size_t)ntt + 2);
   return (b + 15) & ~size_t(15);
 }
 
@@ -250,6 +252,7 @@ __device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int wav
   s.fl = s.a + nbuf;
   s.fr = reinterpret_cast<R*>(s.fl + p.N3 + 2);
   s.q0 = reinterpret_cast<int*>(s.fr + p.N3 + 2);
+  s.st = s.q0 + p.N3 + 2;
   return s;
 }
 
@@ -530,6 +533,43 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
   // the points' grid cells span [qlo, qhi]; an image of the time grid whose
   // tap window misses that span has no contribution
   const int qlo = sm.q0[0], qhi = sm.q0[npt - 1];
+  // st[v] = number of points with q0 < qlo + v (v in [0, span + 1]): a count
+  // per grid cell with integer LDS atomics (the counts do not depend on their
+  // order) and an inclusive prefix sum over the counts stored one cell up;
+  // the bounds of a tap window are then single reads. A span beyond the
+  // table (aliased frequencies) keeps the binary search.
+  const int span = qhi - qlo;
+  const bool table = span <= ntt;
+  int* st = sm.st;
+  if (table) {
+    for (int v = lane; v <= span + 1; v += 64) st[v] = 0;
+    wave_sync();
+    for (int e = lane; e < npt; e += 64) atomicAdd(&st[sm.q0[e] - qlo + 1], 1);
+    wave_sync();
+    const int nv = span + 2, ch = (nv + 63) / 64;
+    const int v0 = lane * ch < nv ? lane * ch : nv;
+    const int v1 = v0 + ch < nv ? v0 + ch : nv;
+    int run = 0;
+    for (int v = v0; v < v1; ++v) run += st[v];
+    int incl = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += t;
+    }
+    int acc = incl - run;
+    for (int v = v0; v < v1; ++v) {
+      acc += st[v];
+      st[v] = acc;
+    }
+    wave_sync();
+  }
+  // first point with q0 >= t
+  auto lower = [&](int t, int from) {
+    if (!table) return lower_bound_i(sm.q0, from, npt, t);
+    const int v = t - qlo;
+    return v <= 0 ? 0 : (v > span ? npt : st[v]);
+  };
   for (int q = lane; q < ntt; q += 64) {
     const int qc = q < ntt / 2 ? q : q - ntt;
     cpx<R> acc = {R(0), R(0)};
@@ -537,8 +577,8 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
       const int qv = qc + m * ntt;
       if (qv + W / 2 - 1 < qlo || qv - W / 2 > qhi) continue;
       // tap o = qv - q0 must lie in [-W/2+1, W/2]: q0 in [qv - W/2, qv + W/2 - 1]
-      const int lo = lower_bound_i(sm.q0, 0, npt, qv - W / 2);
-      const int hi = lower_bound_i(sm.q0, lo, npt, qv + W / 2);
+      const int lo = lower(qv - W / 2, 0);
+      const int hi = lower(qv + W / 2, lo);
       for (int li = lo; li < hi; ++li) {
         const R d = R(qv - sm.q0[li]) - sm.fr[li];
         if constexpr (KBW)

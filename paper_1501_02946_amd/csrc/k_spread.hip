@@ -371,12 +371,27 @@ __global__ __launch_bounds__(256) void k_spread(KP p, const int* __restrict__ ce
 }
 
 // Transpose of the spreading: g'[m][n] = sum_taps s_m phi(q1-u1) phi(q2-u2) U'[q1][q2][n].
-// One wavefront per sensor and time chunk; the W x W taps are read straight
-// from the grid (coalesced along time) and summed in a fixed order.
+// A workgroup's four wavefronts handle four consecutive sensors and one time
+// chunk (64 TT samples, coalesced along time); each sums its W x W taps in a
+// fixed order (along the second axis, then along the first).
+//
+// Neighbouring sensors read mostly the same grid points. When the four tap
+// windows together fit in GC columns and 2W rows, the workgroup stages each
+// row of their union in LDS once (the wavefronts loading its columns in turn)
+// and every wavefront takes its taps from there, so the grid is read from L2
+// about once per workgroup instead of once per sensor. Otherwise each
+// wavefront reads its taps directly. Both paths add the same terms in the
+// same order: the W taps of a row in the data type R (a fixed W-term dot
+// product), the W row sums in the accumulation type A (double for the
+// compensated FP32 path).
 template <int W, int TT, typename R, typename WT, typename A>
 __device__ __forceinline__ void gather_body(const KP& p, int bx, const R* __restrict__ U,
                                             R* __restrict__ g, int vec) {
+  constexpr int GC = W + 12;
+  constexpr int SPAN = 64 * TT;
+  __shared__ __align__(16) R tile[GC * SPAN];
   const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
   // XCD-aware order: each of the 8 XCDs takes a contiguous run of sensor
   // groups of one time chunk, so that neighbouring sensors, which read mostly
   // the same grid rows, share its L2
@@ -386,37 +401,108 @@ __device__ __forceinline__ void gather_body(const KP& p, int bx, const R* __rest
   const int L = (bx & 7) * per + (bx >> 3);
   if (L >= G) return;
   const int chunk = L / ngrp;
-  const int m = __builtin_amdgcn_readfirstlane((L - chunk * ngrp) * 4 + (int)(threadIdx.x >> 6));
-  if (m >= p.M) return;
-  const int Nt = p.Nt;
-  const int tb = chunk * 64 * TT + lane * TT;
+  const int m0 = (L - chunk * ngrp) * 4;
+  const int m = __builtin_amdgcn_readfirstlane(m0 + wv);
+  const bool act = m < p.M;
+  const int Nt = p.Nt, n1 = p.n1, n2 = p.n2;
+  const int tb = chunk * SPAN + lane * TT;
   const int valid = Nt - tb;
   const bool vv = vec != 0;
-  const int c1 = p.cell[2 * m];
-  const int c2 = p.cell[2 * m + 1];
-  const WT* __restrict__ w1 = static_cast<const WT*>(p.w1) + (size_t)m * W;
-  const WT* __restrict__ w2 = static_cast<const WT*>(p.w2) + (size_t)m * W;
+  const WT* __restrict__ w1 = static_cast<const WT*>(p.w1) + (size_t)(act ? m : 0) * W;
+  const WT* __restrict__ w2 = static_cast<const WT*>(p.w2) + (size_t)(act ? m : 0) * W;
+  // cells of the group's sensors relative to the first one (periodic)
+  const int nm = p.M - m0 < 4 ? p.M - m0 : 4;
+  const int b1 = p.cell[2 * m0], b2 = p.cell[2 * m0 + 1];
+  auto rel = [](int d, int n) { return d > n / 2 ? d - n : (d < -n / 2 ? d + n : d); };
+  int r_lo = 0, r_hi = 0, c_lo = 0, c_hi = 0, my1 = 0, my2 = 0;
+  for (int i = 1; i < nm; ++i) {
+    const int d1 = rel(p.cell[2 * (m0 + i)] - b1, n1);
+    const int d2 = rel(p.cell[2 * (m0 + i) + 1] - b2, n2);
+    r_lo = d1 < r_lo ? d1 : r_lo;
+    r_hi = d1 > r_hi ? d1 : r_hi;
+    c_lo = d2 < c_lo ? d2 : c_lo;
+    c_hi = d2 > c_hi ? d2 : c_hi;
+    if (i == wv) {
+      my1 = d1;
+      my2 = d2;
+    }
+  }
+  const int nr = r_hi - r_lo + W, nc = c_hi - c_lo + W;
   A acc[TT];
 #pragma unroll
   for (int t = 0; t < TT; ++t) acc[t] = A(0);
-  for (int k1 = 0; k1 < W; ++k1) {
-    const int row = pmod(c1 + k1 - W / 2 + 1, p.n1);
-    A ra[TT];
+  if (nc <= GC && nr <= 2 * W) {
+    // union row r is grid row b1 + r_lo - W/2 + 1 + r; this sensor's tap k1
+    // sits at union row k1 + my1 - r_lo, its tap k2 at union column k2 + my2 - c_lo
+    const int base_r = b1 + r_lo - W / 2 + 1, base_c = b2 + c_lo - W / 2 + 1;
+    const int k1_0 = my1 - r_lo, k2_0 = my2 - c_lo;
+    // this wavefront stages union columns wv, wv + 4, ...; the next row's
+    // loads are issued before the current row is summed, so their latency
+    // overlaps the sums and the barriers
+    constexpr int SL = (GC + 3) / 4;
+    R nx[SL][TT];
+    auto fetch = [&](int r) {
+      const size_t rowoff = (size_t)pmod(base_r + r, n1) * n2;
 #pragma unroll
-    for (int t = 0; t < TT; ++t) ra[t] = A(0);
+      for (int j = 0; j < SL; ++j) {
+        const int sc = wv + 4 * j;
+        if (sc < nc) load_tt<TT>(nx[j], U + (rowoff + pmod(base_c + sc, n2)) * Nt + tb, valid, vv);
+      }
+    };
+    fetch(0);
+    for (int r = 0; r < nr; ++r) {
 #pragma unroll
-    for (int k2 = 0; k2 < W; ++k2) {
-      const int col = pmod(c2 + k2 - W / 2 + 1, p.n2);
-      R u[TT];
-      load_tt<TT>(u, U + ((size_t)row * p.n2 + col) * Nt + tb, valid, vv);
-      const A wk = A(w2[k2]);
+      for (int j = 0; j < SL; ++j) {
+        const int sc = wv + 4 * j;
+        if (sc < nc) {
 #pragma unroll
-      for (int t = 0; t < TT; ++t) ra[t] += wk * A(u[t]);
+          for (int t = 0; t < TT; ++t) tile[sc * SPAN + lane * TT + t] = nx[j][t];
+        }
+      }
+      __syncthreads();
+      if (r + 1 < nr) fetch(r + 1);
+      const int k1 = r - k1_0;
+      if (act && k1 >= 0 && k1 < W) {
+        R ra[TT];
+#pragma unroll
+        for (int t = 0; t < TT; ++t) ra[t] = R(0);
+#pragma unroll
+        for (int k2 = 0; k2 < W; ++k2) {
+          const R* tp = tile + (k2_0 + k2) * SPAN + lane * TT;
+          const R wk = R(w2[k2]);
+#pragma unroll
+          for (int t = 0; t < TT; ++t) ra[t] += wk * tp[t];
+        }
+        const A wk = A(w1[k1]);
+#pragma unroll
+        for (int t = 0; t < TT; ++t) acc[t] += wk * A(ra[t]);
+      }
+      __syncthreads();
     }
-    const A wk = A(w1[k1]);
+  } else {
+    if (!act) return;
+    const int c1 = p.cell[2 * m];
+    const int c2 = p.cell[2 * m + 1];
+    for (int k1 = 0; k1 < W; ++k1) {
+      const int row = pmod(c1 + k1 - W / 2 + 1, n1);
+      R ra[TT];
 #pragma unroll
-    for (int t = 0; t < TT; ++t) acc[t] += wk * ra[t];
+      for (int t = 0; t < TT; ++t) ra[t] = R(0);
+#pragma unroll
+      for (int k2 = 0; k2 < W; ++k2) {
+        const int col = pmod(c2 + k2 - W / 2 + 1, n2);
+        R u[TT];
+        load_tt<TT>(u, U + ((size_t)row * n2 + col) * Nt + tb, valid, vv);
+        const R wk = R(w2[k2]);
+#pragma unroll
+        for (int t = 0; t < TT; ++t) ra[t] += wk * u[t];
+      }
+      const A wk = A(w1[k1]);
+#pragma unroll
+      for (int t = 0; t < TT; ++t) acc[t] += wk * A(ra[t]);
+    }
   }
+  if (!act) return;
   R o[TT];
 #pragma unroll
   for (int t = 0; t < TT; ++t) o[t] = R(acc[t]);
