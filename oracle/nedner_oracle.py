@@ -97,10 +97,11 @@ def mode_numbers(n: int) -> np.ndarray:
     """Integer mode numbers of a length-n DFT in FFT storage order.
 
     Index k holds mode k for k < n/2 and mode k - n otherwise, i.e. the set
-    {-n/2, ..., n/2-1} of Sec. 2.
+    {-n/2, ..., n/2-1} of Sec. 2 for even n. A single voxel across an axis
+    (the two-dimensional problem, d = 2) carries the mode {0}.
     """
     k = np.arange(n)
-    return np.where(k < n // 2, k, k - n)
+    return np.where(k < (n + 1) // 2, k, k - n)
 
 
 def wavenumbers(geo: Geometry):

@@ -44,6 +44,7 @@ def _tiny_case(seed, m=7, nt=6, n=(4, 6, 8), c=1.3, t0=0.07, a=(0.1, -0.2),
     (1, dict(n=(4, 4, 4), c=1.0, t0=0.0, a=(0.0, 0.0), d=(0.25, 0.25))),
     (2, dict(m=3, nt=8, n=(6, 2, 6), d3=0.04)),
     (3, dict(m=1, nt=2, n=(2, 2, 2))),
+    (4, dict(n=(6, 1, 8), d=(0.3, 1.0))),   # the two-dimensional problem (one voxel across axis 2)
 ])
 def test_spectrum_and_volume_match_brute_force(seed, kw):
     xy, h, g, geo = _tiny_case(seed, **kw)

@@ -38,6 +38,7 @@ def _voxels(geo):
     dict(n=(4, 4, 4), c=1.0, t0=0.0, a=(0.0, 0.0), d=(0.25, 0.25), d3=0.25),
     dict(n=(6, 2, 6), nt=5, d3=0.04),
     dict(n=(2, 2, 2), nt=3),
+    dict(n=(6, 1, 8), d=(0.3, 1.0)),   # two-dimensional problem
 ])
 def test_trace_matches_brute_force(kw):
     geo = _geo(**kw)
