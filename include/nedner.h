@@ -124,7 +124,10 @@ typedef struct {
   const double* h;      /* host, [m] detector areas; NULL => n1 d1 n2 d2 / m each */
   int64_t nt;           /* time samples, even, >= 2 */
   double t0, dt, c;     /* first sample time, time step > 0, sound speed > 0 */
-  int32_t n1, n2, n3;   /* output voxels, each even and >= 2 */
+  int32_t n1, n2, n3;   /* output voxels, each even and >= 2; n2 = 1 is the two-dimensional
+                           problem (sensors on a line along the first axis, image (i1, i3),
+                           the second axis carrying only the mode k2 = 0; not with
+                           NEDNER_EQUISPACED) */
   double a1, a2;        /* aperture origin */
   double d1, d2, d3;    /* voxel steps; d1, d2 > 0; d3 = 0 => c nt dt / n3 */
   int32_t prec;         /* nedner_precision */

@@ -196,8 +196,11 @@ nedner_status validate_impl(const nedner_desc* d, Derived* out) {
   if (d->nt < 2 || (d->nt % 2) || d->nt > (1 << 20)) return fail(NEDNER_E_ARG, "nt must be even and in [2, 2^20]");
   if (!finite(d->t0) || !finite(d->dt) || !(d->dt > 0)) return fail(NEDNER_E_ARG, "t0 must be finite and dt > 0");
   if (!finite(d->c) || !(d->c > 0)) return fail(NEDNER_E_ARG, "c must be finite and > 0");
-  for (int n : {d->n1, d->n2, d->n3})
-    if (n < 2 || (n % 2) || n > (1 << 16)) return fail(NEDNER_E_ARG, "n1, n2, n3 must be even and in [2, 65536]");
+  // n2 = 1 is the two-dimensional problem (d = 2 in Sec. 2): sensors on a line
+  // along the first axis, one voxel across the second, image (i1, i3)
+  auto even_size = [](int n) { return n >= 2 && n % 2 == 0 && n <= (1 << 16); };
+  if (!even_size(d->n1) || !even_size(d->n3) || !(even_size(d->n2) || d->n2 == 1))
+    return fail(NEDNER_E_ARG, "n1, n3 must be even and in [2, 65536]; n2 too, or 1 for the 2-D problem");
   if (!finite(d->a1) || !finite(d->a2)) return fail(NEDNER_E_ARG, "a1, a2 must be finite");
   if (!finite(d->d1) || !finite(d->d2) || !(d->d1 > 0) || !(d->d2 > 0))
     return fail(NEDNER_E_ARG, "d1, d2 must be finite and > 0");
@@ -261,7 +264,9 @@ nedner_status validate_impl(const nedner_desc* d, Derived* out) {
   }
   // frequencies: |omega| dt over the mode set (both Nyquist representatives)
   {
-    const double k1 = M_PI * d->n1 / v.L1, k2 = M_PI * d->n2 / v.L2, kz = M_PI * d->n3 / (d->n3 * v.D3);
+    // (a single voxel across the second axis has only the mode k2 = 0)
+    const double k1 = M_PI * d->n1 / v.L1, k2 = d->n2 == 1 ? 0.0 : M_PI * d->n2 / v.L2;
+    const double kz = M_PI * d->n3 / (d->n3 * v.D3);
     v.max_theta = d->c * d->dt * std::sqrt(k1 * k1 + k2 * k2 + kz * kz);
   }
   // supported transform sizes

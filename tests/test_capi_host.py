@@ -67,12 +67,23 @@ def test_valid_descriptor():
     assert _validate()[0] == 0
 
 
+def test_two_dimensional_descriptor():
+    """n2 = 1: sensors on a line, one voxel across the second axis (d = 2)."""
+    assert _validate(n2=1)[0] == 0
+    info = N.query(np.array([[0.25, 0.5], [0.75, 0.5]]), 64, 1 / 64, (8, 1, 32))
+    assert info["n2_os"] == 2 and info["columns"] == 9
+
+
 @pytest.mark.parametrize("kw,status", [
     (dict(xy=np.zeros((0, 2))), E_ARG),                        # no sensors
     (dict(xy=np.array([[np.nan, 0.5]])), E_ARG),               # non-finite position
     (dict(xy=np.array([[1.0, 0.5]])), E_ARG),                  # outside [a, a+L)
     (dict(xy=np.array([[-0.01, 0.5]])), E_ARG),
     (dict(n1=9), E_ARG),                                       # odd grid
+    (dict(n1=1), E_ARG),                                       # one voxel: only across axis 2
+    (dict(n2=3), E_ARG),
+    (dict(n3=1), E_ARG),
+    (dict(n2=1, xy=np.array([[0.25, 0.5], [0.5, 0.5]]), flags=["equispaced"]), E_ARG),
     (dict(n3=7), E_ARG),
     (dict(nt=63), E_ARG),                                      # odd time count
     (dict(c=0.0), E_ARG),
