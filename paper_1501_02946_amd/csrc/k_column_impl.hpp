@@ -371,7 +371,9 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
   if constexpr (SPEC) {
     cpx<R>* F = static_cast<cpx<R>*>(out);
     const int N1 = p.N1, N2 = p.N2;
-    const bool direct = k2 < N2 / 2 && je < N1;
+    // columns k2 in [0, N2/2) are written as they are (with N2 = 1 the one
+    // row k2 = 0), the others through the Hermitian mirror
+    const bool direct = k2 < (N2 + 1) / 2 && je < N1;
     const bool mirror = k2 >= 1 && je >= 1;
     const size_t rd = ((size_t)pmodc(j1, N1) * N2 + k2) * N3;
     const size_t rm = ((size_t)pmodc(-j1, N1) * N2 + pmodc(-k2, N2)) * N3;
