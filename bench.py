@@ -14,6 +14,8 @@ resident batch of synthetic sensor data. Prints ONE JSON line:
   adjoint      the exact adjoint A* (volume -> data) on the same plan, per stage
   image_measures    the App. B measures of the reconstruction: correlation with
                the rasterised phantom, Tenenbaum sharpness of the depth MIP
+  two_dimensional   the two-dimensional problem (sensors on a line) at the grid
+               of the paper's 2-D study, 1024 x 256
   forward_model_q   the forward operator Q of the wave equation (volume -> data)
                and its adjoint on the same plan, per-stage times, and sampled
                outputs of Q against the oracle
@@ -48,6 +50,8 @@ WORKLOADS = {
           "+ 1% noise -> 240x240x256",
     "c7": "128x128 sensors on the output grid nodes (equispaced, NER-only path), 512 samples, "
           "10 balls + 1% noise -> 128x128x256",
+    "c8": "1024 sensors on a line (two-dimensional problem), 2048 samples, 10 balls + 1% noise "
+          "-> 1024x1x256",
     "c4": "64 problems, M ~ U[1024,16384] jittered, Nt in {256,512,1024}, 1-10 balls, s x s x Nt/2, "
           "one persistent launch per stage",
 }
@@ -312,6 +316,8 @@ def main(argv=None):
                     help="skip the Kaiser-Bessel (8-tap) leg timed beside the headline")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the leg timing the exact adjoint")
+    ap.add_argument("--no-2d", action="store_true",
+                    help="skip the leg timing the two-dimensional problem")
     ap.add_argument("--no-q", action="store_true",
                     help="skip the leg timing the forward operator Q and its adjoint")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -436,6 +442,18 @@ def main(argv=None):
                                  tenenbaum_depth_mip=N.tenenbaum(N.mip(out, 2)),
                                  mip_ms=round(msm, 5))
     del phantom
+    if a.workload == "c2" and not a.no_2d:
+        p2 = synth.config("c8")
+        plan2 = N.Plan(p2.xy, p2.nt, p2.dt, (p2.n1, p2.n2, p2.n3), c=p2.c, h=p2.h, d1=p2.d1,
+                       d2=p2.d2, precision=a.precision)
+        g2 = torch.as_tensor(p2.g, dtype=plan2.dtype, device=plan2.device).contiguous()
+        o2 = torch.empty((p2.n1, p2.n2, p2.n3), dtype=plan2.dtype, device=plan2.device)
+        ms2, _ = time_steps(torch, plan2, g2, o2, a.steps, a.warmup)
+        _, st2 = time_steps(torch, plan2, g2, o2, a.steps, 1, profile=True)
+        res["two_dimensional"] = dict(workload=f"c8: {WORKLOADS['c8']}", ms_per_step=round(ms2, 5),
+                                      value=round(p2.m * p2.nt / (ms2 / 1e3) / 1e6, 2), unit="Mpts/s",
+                                      stages_ms={k: round(v, 5) for k, v in st2.items()})
+        del plan2, g2, o2
     qsample = None
     if not a.no_q:
         # the forward operator Q (initial pressure -> sensor traces) on the

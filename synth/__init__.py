@@ -20,6 +20,9 @@ Workload recipes (all with sound speed c = 1 and aperture [0,1)^2):
 * ``c6``: the equi-steradian mask of App. A: ~1625 sensors snapped to a
   240x240 grid, centre of interest 0.265 above the aperture centre, weights
   h_m ~ r^3; 512 samples, 10 balls, 1 % noise; output 240x240x256.
+* ``c8``: the two-dimensional problem: 1024 sensors on a line (jittered
+  +/-0.4 pitch), 2048 samples, 10 balls centred on the sensors' plane, 1 %
+  noise; output 1024x1x256 (the grid of the paper's 2-D study).
 * ``c7``: 128x128 sensors on the nodes of the 128x128 output grid (the
   equispaced, NER-only case), 512 samples, 10 balls, 1 % noise; output
   128x128x256.
@@ -282,6 +285,16 @@ def config(name: str, seed: int = 0) -> Problem:
         m = xy.shape[0]
         return make_problem(xy, np.full(m, 1.0 / m), balls, 512, 128, 128, 256,
                             rng=rng, noise=0.01, name=name)
+    if name == "c8":
+        # the two-dimensional problem at the size of the paper's 2-D study
+        # (1024 x 256 grid): 1024 sensors on the line y = 0.5, jittered
+        # +/-0.4 pitch, 2048 samples, balls centred on the sensors' plane
+        m = 1024
+        x = (np.arange(m) + 0.5 + rng.uniform(-0.4, 0.4, m)) / m
+        xy = np.stack([x, np.full(m, 0.5)], 1)
+        balls = [(bx, 0.5, bz, r, a) for (bx, _, bz, r, a) in random_balls(10, rng)]
+        return make_problem(xy, np.full(m, 1.0 / m), balls, 2048, 1024, 1, 256,
+                            rng=rng, noise=0.01, name=name, d1=1.0 / 1024, d2=1.0)
     if name == "c5sub":
         xy = jittered_grid(16, 0.4, rng)
         balls = random_balls(3, rng)
