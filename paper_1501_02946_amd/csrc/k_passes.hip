@@ -459,19 +459,63 @@ hipError_t launch_pass_many(const KP& p0, int stage, const BatchProb* bp, const 
                     : pass_many_r<float, false>(p0, stage, bp, wl, smem, s);
 }
 
+// The two-column lateral grid of the two-dimensional problem (n2 = 2, one kept
+// bin k2 = 0): the transform along q2 is the sum of the two columns, and its
+// transpose puts the bin's real part on both. One thread per (q1, sample).
+template <typename R>
+__global__ __launch_bounds__(256) void k_lat_a_two(const R* __restrict__ U, cpx<R>* __restrict__ V, long n1,
+                                                   int Nt) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n1 * Nt) return;
+  const long q1 = i / Nt, t = i - q1 * Nt;
+  V[i] = cpx<R>{U[(2 * q1) * Nt + t] + U[(2 * q1 + 1) * Nt + t], R(0)};
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_a_two(const cpx<R>* __restrict__ V, R* __restrict__ U, long n1,
+                                                   int Nt) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n1 * Nt) return;
+  const long q1 = i / Nt, t = i - q1 * Nt;
+  const R x = V[i].x;
+  U[(2 * q1) * Nt + t] = x;
+  U[(2 * q1 + 1) * Nt + t] = x;
+}
+
+template <typename R>
+static hipError_t run_two(const KP& p, const void* in, void* out, bool adj, hipStream_t s) {
+  const long total = (long)p.n1 * p.Nt;
+  const dim3 grid(unsigned((total + 255) / 256));
+  if (adj)
+    hipLaunchKernelGGL(k_adj_a_two<R>, grid, dim3(256), 0, s, static_cast<const cpx<R>*>(in),
+                       static_cast<R*>(out), (long)p.n1, p.Nt);
+  else
+    hipLaunchKernelGGL(k_lat_a_two<R>, grid, dim3(256), 0, s, static_cast<const R*>(in),
+                       static_cast<cpx<R>*>(out), (long)p.n1, p.Nt);
+  return hipGetLastError();
+}
+
 #define NEDNER_PASS_ENTRY(NAME, KERNEL)                                                   \
   hipError_t NAME(const KP& p, const void* in, void* out, hipStream_t s) {                \
     return p.prec == PREC_FP64 ? run_##KERNEL<double>(p, in, out, s)                      \
                                : run_##KERNEL<float>(p, in, out, s);                      \
   }
 
-NEDNER_PASS_ENTRY(launch_lat_a, k_lat_a)
+hipError_t launch_lat_a(const KP& p, const void* in, void* out, hipStream_t s) {
+  if (p.n2 == 2 && p.K2 == 1)
+    return p.prec == PREC_FP64 ? run_two<double>(p, in, out, false, s) : run_two<float>(p, in, out, false, s);
+  return p.prec == PREC_FP64 ? run_k_lat_a<double>(p, in, out, s) : run_k_lat_a<float>(p, in, out, s);
+}
 NEDNER_PASS_ENTRY(launch_lat_b, k_lat_b)
 NEDNER_PASS_ENTRY(launch_pass_c, k_pass_c)
 NEDNER_PASS_ENTRY(launch_pass_d, k_pass_d)
 NEDNER_PASS_ENTRY(launch_adj_d, k_adj_d)
 NEDNER_PASS_ENTRY(launch_adj_c, k_adj_c)
 NEDNER_PASS_ENTRY(launch_adj_b, k_adj_b)
-NEDNER_PASS_ENTRY(launch_adj_a, k_adj_a)
+hipError_t launch_adj_a(const KP& p, const void* in, void* out, hipStream_t s) {
+  if (p.n2 == 2 && p.K2 == 1)
+    return p.prec == PREC_FP64 ? run_two<double>(p, in, out, true, s) : run_two<float>(p, in, out, true, s);
+  return p.prec == PREC_FP64 ? run_k_adj_a<double>(p, in, out, s) : run_k_adj_a<float>(p, in, out, s);
+}
 
 }  // namespace nedner
