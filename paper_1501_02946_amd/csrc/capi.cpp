@@ -724,6 +724,19 @@ nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* ou
     p->s_unit = dbl ? A.upload(ones) : A.upload_as<float>(ones);
   } else {
     p->w1_unit = wide ? A.upload(G.w1u) : A.upload_as<float>(G.w1u);
+    // the adjoint gather's sensor order: by tiles of 4 x 4 cells, then by cell
+    std::vector<int> order(size_t(desc->m));
+    for (int64_t m = 0; m < desc->m; ++m) order[m] = int(m);
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+      const int x1 = G.cell[2 * size_t(x)], x2 = G.cell[2 * size_t(x) + 1];
+      const int y1 = G.cell[2 * size_t(y)], y2 = G.cell[2 * size_t(y) + 1];
+      if ((x1 >> 2) != (y1 >> 2)) return (x1 >> 2) < (y1 >> 2);
+      if ((x2 >> 2) != (y2 >> 2)) return (x2 >> 2) < (y2 >> 2);
+      if (x1 != y1) return x1 < y1;
+      if (x2 != y2) return x2 < y2;
+      return x < y;
+    });
+    k.gorder = static_cast<const int*>(A.upload(order));
   }
   {
     DevAlloc Lst;

@@ -401,23 +401,28 @@ __device__ __forceinline__ void gather_body(const KP& p, int bx, const R* __rest
   const int L = (bx & 7) * per + (bx >> 3);
   if (L >= G) return;
   const int chunk = L / ngrp;
+  // group members: positions m0 .. m0 + 3 of the gather order (tiles of 4 x 4
+  // cells), so that they are neighbours whatever the sensors' numbering
   const int m0 = (L - chunk * ngrp) * 4;
-  const int m = __builtin_amdgcn_readfirstlane(m0 + wv);
-  const bool act = m < p.M;
+  const int* __restrict__ ord = p.gorder;
+  const bool act = m0 + wv < p.M;
+  const int m = __builtin_amdgcn_readfirstlane(act ? ord[m0 + wv] : 0);
   const int Nt = p.Nt, n1 = p.n1, n2 = p.n2;
   const int tb = chunk * SPAN + lane * TT;
   const int valid = Nt - tb;
   const bool vv = vec != 0;
-  const WT* __restrict__ w1 = static_cast<const WT*>(p.w1) + (size_t)(act ? m : 0) * W;
-  const WT* __restrict__ w2 = static_cast<const WT*>(p.w2) + (size_t)(act ? m : 0) * W;
+  const WT* __restrict__ w1 = static_cast<const WT*>(p.w1) + (size_t)m * W;
+  const WT* __restrict__ w2 = static_cast<const WT*>(p.w2) + (size_t)m * W;
   // cells of the group's sensors relative to the first one (periodic)
   const int nm = p.M - m0 < 4 ? p.M - m0 : 4;
-  const int b1 = p.cell[2 * m0], b2 = p.cell[2 * m0 + 1];
+  const int s0 = ord[m0];
+  const int b1 = p.cell[2 * s0], b2 = p.cell[2 * s0 + 1];
   auto rel = [](int d, int n) { return d > n / 2 ? d - n : (d < -n / 2 ? d + n : d); };
   int r_lo = 0, r_hi = 0, c_lo = 0, c_hi = 0, my1 = 0, my2 = 0;
   for (int i = 1; i < nm; ++i) {
-    const int d1 = rel(p.cell[2 * (m0 + i)] - b1, n1);
-    const int d2 = rel(p.cell[2 * (m0 + i) + 1] - b2, n2);
+    const int si = ord[m0 + i];
+    const int d1 = rel(p.cell[2 * si] - b1, n1);
+    const int d2 = rel(p.cell[2 * si + 1] - b2, n2);
     r_lo = d1 < r_lo ? d1 : r_lo;
     r_hi = d1 > r_hi ? d1 : r_hi;
     c_lo = d2 < c_lo ? d2 : c_lo;

@@ -59,6 +59,8 @@ struct KP {
   const void* ent_w2;  // spreading list: second-axis weight of each entry
   const int* cellbeg;  // [n2 * nseg][CB] list offsets per sweep cell
   const int* node;     // equispaced: [n1 * n2] sensor at each node, -1 where none
+  const int* gorder;   // [M] the sensors in the order the adjoint gather takes them: by tiles
+                       // of 4 x 4 grid cells, so that consecutive sensors are neighbours
   const void* sw;      // equispaced: [M] real: h_m / (d1 d2)
   const void* dec1;    // [J1] real: 1/phihat_1(j1), j1 = -N1/2..N1/2
   const void* dec2;    // [K2] real: 1/phihat_2(k2), k2 = 0..N2/2
