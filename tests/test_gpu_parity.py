@@ -162,3 +162,40 @@ def test_c2_full_volume(torch_gpu):
     plan = make_plan(p, "fp32_plain")
     err = rel_l2(plan(to_dev(p.g, plan)).cpu().numpy(), v)
     print("c2 fp32_plain volume rel-L2", err)
+
+
+@pytest.mark.parametrize("layout", ["iid", "shuffled_grid", "one_cell", "seam", "single"])
+def test_adjoint_and_q_on_unordered_layouts(torch_gpu, layout):
+    """The adjoint gather takes the sensors in the plan's tile order, not in
+    their numbering: sensors numbered at random, packed into one cell, on the
+    periodic seams or alone must give the oracle's adjoint and Q."""
+    rng = np.random.default_rng(12)
+    n = (16, 16, 24)
+    if layout == "iid":
+        xy = rng.uniform(0, 1, size=(300, 2))
+    elif layout == "shuffled_grid":
+        xy = synth.jittered_grid(14, 0.45, rng)[rng.permutation(14 * 14)]
+    elif layout == "one_cell":
+        xy = 0.5 + rng.uniform(0, 1.0 / 32, size=(23, 2))
+    elif layout == "seam":
+        xy = np.array([[1.0 - 1e-13, 0.5], [0.0, 1.0 - 1e-12], [1.0 - 1e-9, 1.0 - 1e-9], [0.25, 0.0],
+                       [0.5, 0.999], [0.001, 0.001], [0.999, 0.2]])
+    else:
+        xy = np.array([[0.37, 0.81]])
+    m = xy.shape[0]
+    nt = 48
+    h = rng.uniform(0.5, 1.5, m)
+    h /= h.sum()
+    p = synth.Problem(xy=xy, h=h, g=np.zeros((m, nt)), nt=nt, dt=1.0 / nt, c=1.0,
+                      n1=n[0], n2=n[1], n3=n[2])
+    geo = geometry_of(p)
+    v = rng.normal(size=n)
+    ref_a = O.adjoint(v, xy, h, geo)
+    ref_q = O.trace(v, xy, geo)
+    for prec in ("fp64", "fp32c"):
+        plan = make_plan(p, prec)
+        vd = to_dev(v, plan)
+        ea = rel_l2(plan.adjoint(vd).cpu().numpy(), ref_a)
+        eq = rel_l2(plan.q(vd).cpu().numpy(), ref_q)
+        print(layout, prec, "adjoint", ea, "Q", eq)
+        assert ea <= TOL and eq <= TOL
