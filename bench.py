@@ -14,6 +14,8 @@ resident batch of synthetic sensor data. Prints ONE JSON line:
   adjoint      the exact adjoint A* (volume -> data) on the same plan, per stage
   image_measures    the App. B measures of the reconstruction: correlation with
                the rasterised phantom, Tenenbaum sharpness of the depth MIP
+  least_squares     20 iterations of projected gradient descent through the
+               autograd functions (model A* and model Q), per-iteration time
   two_dimensional   the two-dimensional problem (sensors on a line) at the grid
                of the paper's 2-D study, 1024 x 256
   forward_model_q   the forward operator Q of the wave equation (volume -> data)
@@ -316,6 +318,8 @@ def main(argv=None):
                     help="skip the Kaiser-Bessel (8-tap) leg timed beside the headline")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the leg timing the exact adjoint")
+    ap.add_argument("--no-lsq", action="store_true",
+                    help="skip the leg timing the projected-gradient least squares")
     ap.add_argument("--no-2d", action="store_true",
                     help="skip the leg timing the two-dimensional problem")
     ap.add_argument("--no-q", action="store_true",
@@ -442,6 +446,21 @@ def main(argv=None):
                                  tenenbaum_depth_mip=N.tenenbaum(N.mip(out, 2)),
                                  mip_ms=round(msm, 5))
     del phantom
+    if not a.no_lsq:
+        # the step is fixed from a power iteration before the timed region
+        lsq_res = {}
+        for model in ("adjoint", "q"):
+            eta = 0.95 / max(N.power_norm(plan, iters=20, model=model), 1e-300)
+            rhs = g if model == "adjoint" else plan.q(out)
+            N.lsq(plan, rhs, iters=2, eta=eta, model=model)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, losses = N.lsq(plan, rhs, iters=20, eta=eta, model=model)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            lsq_res[model] = dict(ms_per_iteration=round(dt * 1e3 / 20, 4),
+                                  loss_ratio=float(losses[-1] / losses[0]) if losses[0] else None)
+        res["least_squares"] = lsq_res
     if a.workload == "c2" and not a.no_2d:
         p2 = synth.config("c8")
         plan2 = N.Plan(p2.xy, p2.nt, p2.dt, (p2.n1, p2.n2, p2.n3), c=p2.c, h=p2.h, d1=p2.d1,
