@@ -199,17 +199,39 @@ def ball_signal(xy: np.ndarray, times: np.ndarray, balls, c: float = 1.0,
     Closed form of the wave problem in Sec. 2 for a uniform ball seen from
     outside it: p(r,t) = p0 (r - c t)/(2 r) when |r - c t| <= R, else 0, with r
     the sensor-to-centre distance. Signals of several balls add.
+
+    A ball reaches a sensor only during 2R/c of the record, so each ball's
+    trace is evaluated on the samples of that window alone (a candidate range
+    one sample wider on each side, then the exact test |r - c t| <= R); the
+    values are the same expressions as on the whole record. `chunk` is kept
+    for callers that pass it.
     """
     xy = np.asarray(xy, dtype=np.float64)
     t = np.asarray(times, dtype=np.float64)
-    out = np.zeros((xy.shape[0], t.shape[0]))
-    ct = c * t[None, :]
+    nt = t.shape[0]
+    out = np.zeros((xy.shape[0], nt))
+    if nt == 0 or xy.shape[0] == 0:
+        return out
+    ct = c * t
+    t0 = float(t[0])
+    step = float(t[1] - t[0]) if nt > 1 else 1.0
     for (bx, by, bz, R, p0) in balls:
-        for s0 in range(0, xy.shape[0], chunk):
-            sl = slice(s0, s0 + chunk)
-            r = np.sqrt((xy[sl, 0] - bx) ** 2 + (xy[sl, 1] - by) ** 2 + bz * bz)[:, None]
-            d = r - ct
-            out[sl] += np.where(np.abs(d) <= R, p0 * d / (2.0 * r), 0.0)
+        r = np.sqrt((xy[:, 0] - bx) ** 2 + (xy[:, 1] - by) ** 2 + bz * bz)
+        lo = np.clip(np.floor(((r - R) / c - t0) / step).astype(np.int64) - 1, 0, nt)
+        hi = np.clip(np.ceil(((r + R) / c - t0) / step).astype(np.int64) + 1, -1, nt - 1)
+        cnt = np.maximum(hi - lo + 1, 0)
+        tot = int(cnt.sum())
+        if tot == 0:
+            continue
+        # one entry per (sensor, candidate sample): sensor ri, sample ni
+        ri = np.repeat(np.arange(xy.shape[0]), cnt)
+        first = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        ni = np.repeat(lo, cnt) + (np.arange(tot) - first)
+        rr = r[ri]
+        d = rr - ct[ni]
+        keep = np.abs(d) <= R
+        # (sensor, sample) pairs are distinct within one ball
+        out[ri[keep], ni[keep]] += p0 * d[keep] / (2.0 * rr[keep])
     return out
 
 
