@@ -3,27 +3,30 @@
 
 One step = one forward execute of the whole operator (spread, lateral FFTs and
 deconvolution, NER column FFT + gather + weight, inverse 3D FFT) on one
-resident batch of synthetic sensor data. Prints ONE JSON line:
+resident batch of synthetic sensor data. The default workload is the largest
+single-GPU one: 65536 sensors drawn 4x denser near the aperture centre, 1024
+samples, 30 balls and 5 bead-chain cylinders, output 256x256x512, in the
+compensated FP32 precision. Prints ONE JSON line:
 
   value        non-uniform points per second, M * Nt / t_step, in Mpts/s
   roofline     the slowest kernel against its bound (HBM bytes or ALU flops),
                timed live with HIP events on the execute stream
-  cpu_baseline the FP64 oracle timed on the host on the same workload
-  fp64_plain   the same operator in FP64 on the GPU, and the FP32 speedup
-  kaiser_bessel_w8  the same workload with the Kaiser-Bessel window at 8 taps
-  adjoint      the exact adjoint A* (volume -> data) on the same plan, per stage
-  image_measures    the App. B measures of the reconstruction: correlation with
-               the rasterised phantom, Tenenbaum sharpness of the depth MIP
-  least_squares     20 iterations of projected gradient descent through the
-               autograd functions (model A* and model Q), per-iteration time
-  two_dimensional   the two-dimensional problem (sensors on a line) at the grid
-               of the paper's 2-D study, 1024 x 256
-  forward_model_q   the forward operator Q of the wave equation (volume -> data)
-               and its adjoint on the same plan, per-stage times, and sampled
-               outputs of Q against the oracle
-
-Inputs: 128x128 jittered sensors (+/-0.45 pitch), 512 samples, 10 random balls
-and 1 % noise, output 128x128x256 (the FP32-vs-plain comparison workload).
+  cpu_baseline the FP64 oracle timed on the host on the whole workload, and the
+               rel-L2 of every GPU precision against its volume
+  fp64_plain, fp32_plain, fp32   the same operator in the other precisions:
+               time, speedup of the headline precision, rel-L2
+  kaiser_bessel_w8   the Kaiser-Bessel window at 8 taps on the same data
+  adjoint      the exact adjoint A* (volume -> data) on the same plan
+  forward_model_q    the forward operator Q of the wave equation and Q*
+  image_measures     App. B measures of the reconstruction
+  least_squares      20 projected-gradient iterations through the autograd
+               functions on the 192x192-sensor workload, device time
+  cache_resident_c2  the 128x128-sensor workload (its 202 MB workspace fits
+               in the 256 MB Infinity Cache), with its own oracle error
+  two_dimensional    sensors on a line, 1024 x 256 grid
+  batch_c4     64 reconstructions of uneven size in one persistent launch per
+               stage: aggregate roofline, oracle baseline, max rel-L2
+  paper_timings      the paper's own reconstruction times (hardware not stated)
 """
 from __future__ import annotations
 
@@ -42,10 +45,11 @@ METRIC = "NEDNER-NUFFT recon Mpts/s & %HBM roofline, FP32 vs FP64 plain at rel e
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 FP32_VECTOR_TFLOPS = 157.3
+ORACLE_WORKERS = 16
 
 WORKLOADS = {
-    "c2": "128x128 sensors jittered +/-0.45 pitch, 512 samples, 10 balls + 1% noise -> 128x128x256",
     "c3": "65536 sensors 4x denser near the centre, 1024 samples, 30 balls + 5 bead chains -> 256x256x512",
+    "c2": "128x128 sensors jittered +/-0.45 pitch, 512 samples, 10 balls + 1% noise -> 128x128x256",
     "c5": "192x192 sensors jittered +/-0.4 pitch, 768 samples, 20 balls + 1% noise -> 192x192x384",
     "c1": "32x32 sensors jittered +/-0.4 pitch, 128 samples, one ball -> 32x32x64",
     "c6": "equi-steradian mask: ~1600 sensors on a 240x240 grid, h ~ r^3, 512 samples, 10 balls "
@@ -58,15 +62,43 @@ WORKLOADS = {
           "one persistent launch per stage",
 }
 
+# Reconstruction times the paper reports (Sec. 4, Table 1; Sec. 7). It names
+# neither the hardware nor the precision of these runs.
+PAPER_TIMINGS = [
+    dict(workload="star target, Fabry-Perot scan", method="NER-NUFFT, K = 6", seconds=140.0,
+         source="Sec. 4, Table 1", hardware="not stated"),
+    dict(workload="star target", method="k-Wave FFT + linear interpolation", seconds=189.0,
+         source="Sec. 4, Table 1", hardware="not stated"),
+    dict(workload="USAF chart, 146x146 sensors", method="NER-NUFFT", seconds=298.0,
+         source="Sec. 4, Table 1", hardware="not stated"),
+    dict(workload="USAF chart", method="k-Wave FFT + linear interpolation", seconds=384.0,
+         source="Sec. 4, Table 1", hardware="not stated"),
+    dict(workload="yarn, 226x226 = 51076 sensors, 452x452 lateral output", method="NER-NUFFT",
+         seconds=154.0, source="Sec. 7", hardware="not stated"),
+    dict(workload="yarn, equi-steradian mask of 1625 sensors", method="NEDNER-NUFFT",
+         seconds=134.0, source="Sec. 7", hardware="not stated"),
+]
 
-def stage_model(p, info, prec, equi=False):
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def stage_model(p, info, prec, equi=False, w=12):
     """Algorithmic bytes and flops of each forward stage (one launch each).
     On the equispaced path the spreading is a placement: one product per sample."""
     rs = 8 if prec == "fp64" else 4
     cs = 2 * rs
     M, Nt, N1, N2, N3 = p.m, p.nt, p.n1, p.n2, p.n3
     n1, n2, ntt = info["n1_os"], info["n2_os"], info["nt_os"]
-    K2, J1, W = N2 // 2 + 1, N1 + 1, 12
+    K2, J1, W = N2 // 2 + 1, N1 + 1, w
     return {
         "spread": dict(bytes=rs * M * Nt + rs * n1 * n2 * Nt,
                        flops=M * Nt if equi else 2 * W * W * M * Nt),
@@ -84,9 +116,25 @@ def stage_model(p, info, prec, equi=False):
     }
 
 
+def adjoint_stage_model(p, info, prec, w=12):
+    """Algorithmic bytes of the adjoint stages (the forward stages' transposes)."""
+    fw = stage_model(p, info, prec, w=w)
+    rs = 8 if prec == "fp64" else 4
+    return {"adj_d": fw["pass_d"], "adj_c": fw["pass_c"], "column_adj": fw["column"],
+            "adj_b": fw["lat_b"], "adj_a": fw["lat_a"],
+            "gather": dict(bytes=rs * p.m * p.nt + rs * info["n1_os"] * info["n2_os"] * p.nt,
+                           flops=2 * w * w * p.m * p.nt)}
+
+
+def spread_peak(prec):
+    """ALU peak of the spreading's multiply-adds: FP64 vector for FP64 sums,
+    the chip's FP32 vector peak (packed issue) for FP32 sums."""
+    return FP64_VECTOR_TFLOPS if prec in ("fp64", "fp32w") else FP32_VECTOR_TFLOPS
+
+
 # kernel name prefix -> stage, and the source file that defines the kernel
 STAGE_KERNELS = {
-    "k_spread": ("spread", "k_spread.hip"), "k_lat_a": ("lat_a", "k_passes.hip"),
+    "k_spread": ("spread", "k_spread_impl.hpp"), "k_lat_a": ("lat_a", "k_passes.hip"),
     "k_lat_b": ("lat_b", "k_passes.hip"), "k_column": ("column", "k_column_impl.hpp"),
     "k_pass_c": ("pass_c", "k_passes.hip"), "k_pass_d": ("pass_d", "k_passes.hip"),
 }
@@ -134,7 +182,7 @@ def summarize_counters(root, workload, prec, tuning):
     """HBM traffic per stage from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)
     of this script, each scaled by what the same counter reads for a plain
     device copy of known size (the --copy-calibration run)."""
-    out, lines = {}, []
+    out = {}
     scale = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         cal = _counter_means(os.path.join(root, f"pmc_{c}", "copy_counter_collection.csv"))
@@ -146,8 +194,7 @@ def summarize_counters(root, workload, prec, tuning):
     fetch = _counter_means(os.path.join(root, "pmc_FETCH_SIZE", f"{workload}_counter_collection.csv"))
     write = _counter_means(os.path.join(root, "pmc_WRITE_SIZE", f"{workload}_counter_collection.csv"))
     for kname, (stage, _) in STAGE_KERNELS.items():
-        hit = [k for k in fetch if k == kname]
-        if not hit or kname not in write:
+        if kname not in fetch or kname not in write:
             continue
         fk, n = fetch[kname]
         wk, _ = write[kname]
@@ -159,13 +206,10 @@ def summarize_counters(root, workload, prec, tuning):
     return out
 
 
-def time_steps(torch, plan, g, out, steps, warmup, profile=False):
-    return time_op(torch, plan, lambda: plan.forward(g, out=out), steps, warmup, profile)
-
-
 def time_op(torch, plan, fn, steps, warmup, profile=False):
     """Mean time of fn() (one operator call on the plan's stream) over `steps`
-    calls, HIP events around them; with profile, the plan's stage times too."""
+    calls, HIP events around them on that stream; with profile, the plan's
+    per-stage times (HIP events recorded by the library between its kernels)."""
     import ctypes
     import paper_1501_02946_amd as N
     for _ in range(warmup):
@@ -192,25 +236,76 @@ def time_op(torch, plan, fn, steps, warmup, profile=False):
     return ms, stages
 
 
-def cpu_baseline(p, leg_limit_s=60.0):
-    """The FP64 oracle on the host: full forward operator on the same workload."""
-    import numpy as np
+def roofline_of(stages, model, prec, equi=False):
+    """The slowest stage against its bound: the spreading's multiply-adds
+    against the ALU peak of its accumulation type, every other stage's
+    algorithmic bytes against the HBM peak."""
+    dom = max(stages, key=stages.get)
+    tdom = stages[dom] / 1e3
+    if dom in ("spread", "gather") and not equi:
+        peak = spread_peak(prec)
+        ach = model[dom]["flops"] / tdom / 1e12
+        roof = dict(bound="alu", achieved=round(ach, 3), peak=peak, unit="TFLOP/s",
+                    frac=round(ach / peak, 4))
+    else:
+        ach = model[dom]["bytes"] / tdom / 1e9
+        roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4))
+    roof["kernel"] = dom
+    roof["ms"] = round(stages[dom], 5)
+    roof["alg_bytes"] = model[dom]["bytes"]
+    roof["alg_flops"] = model[dom]["flops"]
+    return roof
+
+
+def stage_report(stages, model):
+    rep = {}
+    for name, t in stages.items():
+        m = model.get(name, {})
+        gbs = m.get("bytes", 0) / (t / 1e3) / 1e9 if t > 0 else 0.0
+        rep[name] = dict(ms=round(t, 5), alg_bytes=m.get("bytes"), alg_flops=m.get("flops"),
+                         hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+    return rep
+
+
+# ---------------------------------------------------------------- oracle side
+
+def _limit_threads():
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+        os.environ[k] = "1"
+
+
+def _oracle_volume_task(args):
+    """Worker: the oracle volume of one problem (one BLAS thread per worker)."""
+    idx, xy, h, g, geo_kw = args
     import oracle as O
+    geo = O.geometry(**geo_kw)
+    t = time.perf_counter()
+    v = O.forward(xy, h, g, geo)
+    return idx, v, time.perf_counter() - t
+
+
+def blas_threads() -> int:
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
     except Exception:
-        threads = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def oracle_full(p):
+    """The FP64 oracle on the whole workload in this process: volume and time."""
+    import oracle as O
     geo = O.geometry(**p.geometry_kwargs())
     t = time.perf_counter()
     F = O.spectrum(p.xy, p.h, p.g, geo)
     v = O.volume_from_spectrum(F)
-    dt = time.perf_counter() - t
-    return v, dict(value=p.m * p.nt / dt / 1e6, unit="Mpts/s", cores=int(threads), kind="oracle",
-                   seconds=round(dt, 3),
-                   sample=(f"the full workload ({p.m} sensors x {p.nt} samples -> "
-                           f"{p.n1}x{p.n2}x{p.n3}): NED as BLAS GEMMs on {threads} threads, "
-                           "NER by Horner's rule (numpy, one thread), numpy ifftn"))
+    return v, time.perf_counter() - t
+
+
+def rel_l2(a, ref):
+    import numpy as np
+    return float(np.linalg.norm(a.astype(np.float64) - ref) / max(float(np.linalg.norm(ref)), 1e-300))
 
 
 def q_sample_error(p, vol, dq, nsens=48, ntimes=4, seed=3):
@@ -232,10 +327,68 @@ def q_sample_error(p, vol, dq, nsens=48, ntimes=4, seed=3):
     return float(np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300))
 
 
-def bench_batch(a, torch, N, synth):
-    """The 64-problem batch: one execute_many per step."""
+# ---------------------------------------------------------------- legs
+
+def make_plan(N, p, precision, **kw):
+    return N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0, a1=p.a1, a2=p.a2,
+                  d1=p.d1, d2=p.d2, d3=p.d3, precision=precision, **kw)
+
+
+def leg_precision(torch, N, p, prec, a, flags=(), tuning=None, **kw):
+    """Time one precision on the workload (with the given launch shape, else
+    the plan's default); returns (record, volume on the host)."""
+    plan = make_plan(N, p, prec, flags=list(flags), **kw)
+    if tuning:
+        plan.set_tuning(tuning)
+    g = torch.as_tensor(p.g, dtype=plan.dtype, device=plan.device).contiguous()
+    out = torch.empty((p.n1, p.n2, p.n3), dtype=plan.dtype, device=plan.device)
+    ms, _ = time_op(torch, plan, lambda: plan.forward(g, out=out), a.steps, a.warmup)
+    _, st = time_op(torch, plan, lambda: plan.forward(g, out=out), a.steps, 1, profile=True)
+    rec = dict(ms_per_step=round(ms, 5), value=round(p.m * p.nt / (ms / 1e3) / 1e6, 2),
+               unit="Mpts/s", stages_ms={k: round(v, 5) for k, v in st.items()})
+    vol = out.cpu().numpy()
+    del plan, g, out
+    return rec, vol
+
+
+def leg_least_squares(torch, N, a):
+    """20 projected-gradient iterations on the 192x192-sensor workload through the
+    autograd functions (model A* and model Q), timed with HIP events on the
+    stream the operators run on; the losses stay on the device until the end."""
+    import synth
+    p = synth.config("c5")
+    plan = make_plan(N, p, a.precision)
+    g = torch.as_tensor(p.g, dtype=plan.dtype, device=plan.device).contiguous()
+    res = {"workload": f"c5: {WORKLOADS['c5']}"}
+    iters = 20
+    for model in ("adjoint", "q"):
+        # the step is fixed from a power iteration before the timed region
+        eta = 0.95 / max(N.power_norm(plan, iters=20, model=model), 1e-300)
+        rhs = g if model == "adjoint" else plan.q(plan.forward(g))
+        N.lsq(plan, rhs, iters=2, eta=eta, model=model)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream(plan.device)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, losses = N.lsq(plan, rhs, iters=iters, eta=eta, model=model, sync=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / iters
+        losses = [float(v) for v in losses]
+        res[model] = dict(ms_per_iteration=round(ms, 4), iterations=iters,
+                          loss_ratio=float(losses[-1] / losses[0]) if losses[0] else None,
+                          monotone=bool(all(b <= a_ * (1 + 1e-6) for a_, b in zip(losses, losses[1:]))))
+    del plan, g
+    return res
+
+
+def leg_batch(torch, N, a, probs, pool):
+    """The 64-problem batch: one execute_many per step; aggregate roofline;
+    the oracle over every problem in worker processes (one per host thread)."""
     import ctypes
-    probs = synth.batch_c4()
+
+    import numpy as np
     kws = [dict(xy=p.xy, h=p.h, nt=p.nt, dt=p.dt, volume=(p.n1, p.n2, p.n3)) for p in probs]
     bp = N.BatchPlan(kws, precision=a.precision)
     tune = bp.autotune()
@@ -246,28 +399,61 @@ def bench_batch(a, torch, N, synth):
         bp(gs, outs)
     torch.cuda.synchronize()
     N._check(N.lib().nedner_profile_begin(bp._plan, a.steps))
+    stream = torch.cuda.current_stream(bp.device)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
+    t0.record(stream)
     for _ in range(a.steps):
         bp(gs, outs)
-    t1.record()
+    t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / a.steps
     arr = (ctypes.c_double * 16)()
     ns = ctypes.c_int(0)
     names = ctypes.c_char_p()
     N._check(N.lib().nedner_profile_end(bp._plan, arr, 16, ctypes.byref(ns), ctypes.byref(names)))
-    stages = dict(zip(names.value.decode().split(","), [round(arr[i], 5) for i in range(ns.value)]))
+    stages = dict(zip(names.value.decode().split(","), [arr[i] for i in range(ns.value)]))
+    vols = [o.cpu().numpy() for o in outs]
     points = sum(p.m * p.nt for p in probs)
-    return {"metric": METRIC, "value": round(points / (ms / 1e3) / 1e6, 2), "unit": "Mpts/s",
-            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 5),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
-            "config": {"workload": f"c4: {WORKLOADS['c4']}", "problems": len(probs),
-                       "points": points, "precision": a.precision},
-            "volumes_per_s": round(len(probs) * 1e3 / ms, 2), "stages_ms": stages,
-            "autotune": tune, "roofline": None, "cpu_baseline": None}
+    # aggregate algorithmic bytes and flops of each stage over the problems
+    agg = {}
+    for p in probs:
+        info = N.query(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), h=p.h, precision=a.precision)
+        for k, v in stage_model(p, info, a.precision).items():
+            s = agg.setdefault(k, dict(bytes=0, flops=0))
+            s["bytes"] += v["bytes"]
+            s["flops"] += v["flops"]
+    roof = roofline_of(stages, agg, a.precision)
+    total_bytes = sum(v["bytes"] for v in agg.values())
+    rec = {"workload": f"c4: {WORKLOADS['c4']}", "problems": len(probs), "points": points,
+           "ms_per_step": round(ms, 5), "value": round(points / (ms / 1e3) / 1e6, 2), "unit": "Mpts/s",
+           "volumes_per_s": round(len(probs) * 1e3 / ms, 2),
+           "spread_ps_per_sample": round(stages.get("spread", 0.0) * 1e9 / points, 3),
+           "stages_ms": {k: round(v, 5) for k, v in stages.items()},
+           "stage_hbm_frac": {k: round(agg[k]["bytes"] / (stages[k] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                              for k in stages if k in agg and stages[k] > 0},
+           "whole_step_hbm_frac": round(total_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "autotune": tune, "roofline": roof}
+    del bp, gs, outs
+    if pool is not None:
+        t = time.perf_counter()
+        tasks = [(i, p.xy, p.h, p.g, p.geometry_kwargs()) for i, p in enumerate(probs)]
+        # largest problems first, so that the last ones to finish are small
+        tasks.sort(key=lambda tk: -(tk[3].size * tk[1].shape[0]))
+        errs = [None] * len(probs)
+        busy = 0.0
+        for i, v, sec in pool.imap_unordered(_oracle_volume_task, tasks):
+            errs[i] = rel_l2(vols[i], v)
+            busy += sec
+        wall = time.perf_counter() - t
+        rec["max_rel_l2_vs_oracle"] = max(errs)
+        rec["worst_problem"] = int(np.argmax(errs))
+        rec["cpu_baseline"] = dict(
+            value=round(points / wall / 1e6, 4), unit="Mpts/s", cores=ORACLE_WORKERS, kind="oracle",
+            seconds=round(wall, 2), cpu_model=cpu_model(),
+            sample=(f"all {len(probs)} problems, each on one worker process with one BLAS thread, "
+                    f"{ORACLE_WORKERS} workers; {busy:.0f} worker-seconds"))
+    return rec
 
 
 def write_traffic(a):
@@ -310,20 +496,22 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp32_plain", "fp64"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-kb", action="store_true",
-                    help="skip the Kaiser-Bessel (8-tap) leg timed beside the headline")
-    ap.add_argument("--no-adjoint", action="store_true",
-                    help="skip the leg timing the exact adjoint")
-    ap.add_argument("--no-lsq", action="store_true",
-                    help="skip the leg timing the projected-gradient least squares")
-    ap.add_argument("--no-2d", action="store_true",
-                    help="skip the leg timing the two-dimensional problem")
-    ap.add_argument("--no-q", action="store_true",
-                    help="skip the leg timing the forward operator Q and its adjoint")
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32c", "fp32w", "fp32", "fp32_plain", "fp64"])
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the plan's default launch shape instead of the autotuner's")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline and stage times only (no other legs, no oracle)")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip every oracle run")
+    ap.add_argument("--no-precisions", action="store_true",
+                    help="skip the FP64-plain, FP32-plain and FP32 legs")
+    ap.add_argument("--no-kb", action="store_true", help="skip the Kaiser-Bessel (8-tap) leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the exact adjoint leg")
+    ap.add_argument("--no-q", action="store_true", help="skip the forward operator Q leg")
+    ap.add_argument("--no-lsq", action="store_true", help="skip the least-squares leg")
+    ap.add_argument("--no-c2", action="store_true", help="skip the cache-resident c2 leg")
+    ap.add_argument("--no-2d", action="store_true", help="skip the two-dimensional leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
@@ -331,6 +519,13 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.summarize_counters:
         return write_traffic(a)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): this build has no multi-GPU "
+              "path; how the operator would shard is a design note", file=sys.stderr)
+        return 2
+    if a.quick:
+        a.no_cpu_baseline = a.no_precisions = a.no_kb = a.no_adjoint = a.no_q = True
+        a.no_lsq = a.no_c2 = a.no_2d = a.no_batch = True
     if a.copy_calibration:
         import torch
         x = torch.ones(a.copy_calibration * (1 << 18), dtype=torch.float32, device="cuda")
@@ -340,10 +535,13 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": x.numel() * 4, "launches": 3}), flush=True)
         return 0
-    if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU split of the "
-              "operator is a design note, not part of this build", file=sys.stderr)
-        return 2
+
+    pool = None
+    if not a.no_cpu_baseline and not a.no_batch and a.workload != "c4":
+        # oracle workers for the batch: fresh interpreters, started before this
+        # process touches the GPU, one BLAS thread each
+        import multiprocessing as mp
+        pool = mp.get_context("spawn").Pool(ORACLE_WORKERS, initializer=_limit_threads)
 
     import numpy as np
     import torch
@@ -352,46 +550,38 @@ def main(argv=None):
     import synth
 
     if a.workload == "c4":
-        print(json.dumps(bench_batch(a, torch, N, synth)), flush=True)
+        rec = leg_batch(torch, N, a, synth.batch_c4(), None)
+        res = {"metric": METRIC, "value": rec["value"], "unit": "Mpts/s", "n_gpus": 1, "steps": a.steps,
+               "warmup": a.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32",
+               "data": "synthetic", "config": {"workload": rec["workload"], "precision": a.precision},
+               "roofline": rec["roofline"], "cpu_baseline": None, "batch": rec}
+        print(json.dumps(res), flush=True)
         return 0
+
     p = synth.config(a.workload)
     equi = a.workload == "c7"
     flags = ["equispaced"] if equi else []
-    plan = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0,
-                  precision=a.precision, flags=flags)
+    plan = make_plan(N, p, a.precision, flags=flags)
     g = torch.as_tensor(p.g, dtype=plan.dtype, device=plan.device).contiguous()
     out = torch.empty((p.n1, p.n2, p.n3), dtype=plan.dtype, device=plan.device)
+    if not a.no_autotune and not equi:
+        # launch shape by timing candidates (sweep length, samples per lane,
+        # FFT-pass shape) before the timed region; the legs below reuse it
+        import tempfile
+        plan.autotune(g, cache=os.path.join(tempfile.mkdtemp(prefix="nedner_bench_"), "tuning.json"))
 
-    ms, _ = time_steps(torch, plan, g, out, a.steps, a.warmup)
-    _, stages = time_steps(torch, plan, g, out, a.steps, 1, profile=True)
+    ms, _ = time_op(torch, plan, lambda: plan.forward(g, out=out), a.steps, a.warmup)
+    _, stages = time_op(torch, plan, lambda: plan.forward(g, out=out), a.steps, 1, profile=True)
     vol = out.cpu().numpy()
     points = p.m * p.nt
     value = points / (ms / 1e3) / 1e6
 
     model = stage_model(p, plan.info, a.precision, equi)
-    stage_rep = {}
-    for name, t in stages.items():
-        m = model.get(name, {})
-        gbs = m.get("bytes", 0) / (t / 1e3) / 1e9 if t > 0 else 0.0
-        stage_rep[name] = dict(ms=round(t, 5), alg_bytes=m.get("bytes"), alg_flops=m.get("flops"),
-                               hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
-    dom = max(stages, key=stages.get)
-    tdom = stages[dom] / 1e3
-    if dom == "spread" and not equi:
-        # the spread is a W*W-tap multiply-add per (sensor, sample): ALU bound;
-        # the compensated and FP64 paths accumulate with FP64 FMAs
-        peak = FP64_VECTOR_TFLOPS if a.precision in ("fp32c", "fp64") else FP32_VECTOR_TFLOPS
-        ach = model[dom]["flops"] / tdom / 1e12
-        roof = dict(bound="alu", achieved=round(ach, 3), peak=peak, unit="TFLOP/s",
-                    frac=round(ach / peak, 4))
-    else:
-        ach = model[dom]["bytes"] / tdom / 1e9
-        roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4))
-    roof["kernel"] = dom
-    roof["ms"] = round(stages[dom], 5)
+    roof = roofline_of(stages, model, a.precision, equi)
     tuning = {k: v for k, v in plan.tuning.items() if not k.startswith("ms_")}
-    roof["traffic"] = measured_traffic(a.workload, a.precision, dom, tuning)
+    roof["traffic"] = measured_traffic(a.workload, a.precision, roof["kernel"], tuning)
+    whole_bytes = sum(v["bytes"] for v in model.values())
 
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1,
@@ -402,84 +592,51 @@ def main(argv=None):
                    "nt": p.nt, "volume": [p.n1, p.n2, p.n3], "precision": a.precision,
                    "window_taps": 12, "oversampling": 2},
         "volumes_per_s": round(1e3 / ms, 2),
+        "whole_step_hbm_frac": round(whole_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "tuning": tuning,
         "roofline": roof,
-        "stages": stage_rep,
+        "stages": stage_report(stages, model),
     }
-    if not a.no_fp64 and a.precision != "fp64":
-        p64 = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0, precision="fp64",
-                     flags=flags)
-        g64 = torch.as_tensor(p.g, dtype=torch.float64, device=plan.device).contiguous()
-        o64 = torch.empty((p.n1, p.n2, p.n3), dtype=torch.float64, device=plan.device)
-        ms64, _ = time_steps(torch, p64, g64, o64, a.steps, a.warmup)
-        res["fp64_plain"] = dict(ms_per_step=round(ms64, 5), value=round(points / (ms64 / 1e3) / 1e6, 2),
-                                 fp32_speedup=round(ms64 / ms, 3))
-        vol64 = o64.cpu().numpy()
-        del p64
-    else:
-        vol64 = None
-    volkb = None
+    vols = {}
+    shape = {k: v for k, v in tuning.items()}
+    if not a.no_precisions:
+        for prec in ("fp64", "fp32_plain", "fp32c", "fp32w", "fp32"):
+            if prec == a.precision:
+                continue
+            key = {"fp64": "fp64_plain", "fp32_plain": "fp32_plain", "fp32c": "fp32_compensated",
+                   "fp32w": "fp32_wide_sums", "fp32": "fp32"}[prec]
+            rec, vols[key] = leg_precision(torch, N, p, prec, a, flags, tuning=shape)
+            rec[f"{a.precision}_speedup"] = round(rec["ms_per_step"] / ms, 3)
+            res[key] = rec
     if not a.no_kb:
         # the paper's window choice: Kaiser-Bessel, 8 taps per axis instead of 12
-        pkb = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0,
-                     precision=a.precision, w=8, window="kaiser_bessel", flags=flags)
-        okb = torch.empty((p.n1, p.n2, p.n3), dtype=plan.dtype, device=plan.device)
-        mskb, _ = time_steps(torch, pkb, g, okb, a.steps, a.warmup)
-        _, stkb = time_steps(torch, pkb, g, okb, a.steps, 1, profile=True)
-        res["kaiser_bessel_w8"] = dict(ms_per_step=round(mskb, 5),
-                                       value=round(points / (mskb / 1e3) / 1e6, 2),
-                                       stages_ms={k: round(v, 5) for k, v in stkb.items()})
-        volkb = okb.cpu().numpy()
-        del pkb
+        rec, vols["kaiser_bessel_w8"] = leg_precision(torch, N, p, a.precision, a, flags, tuning=shape, w=8,
+                                                      window="kaiser_bessel")
+        res["kaiser_bessel_w8"] = rec
     if not a.no_adjoint:
         # the exact adjoint (a transpose pass of every stage) on the reconstructed volume
         da = torch.empty((p.m, p.nt), dtype=plan.dtype, device=plan.device)
         msa, _ = time_op(torch, plan, lambda: plan.adjoint(out, out=da), a.steps, a.warmup)
         _, sta = time_op(torch, plan, lambda: plan.adjoint(out, out=da), a.steps, 1, profile=True)
+        amodel = adjoint_stage_model(p, plan.info, a.precision)
         res["adjoint"] = dict(ms_per_step=round(msa, 5), value=round(points / (msa / 1e3) / 1e6, 2),
-                              unit="Mpts/s", stages_ms={k: round(v, 5) for k, v in sta.items()})
+                              unit="Mpts/s", ratio_to_forward=round(msa / ms, 3),
+                              stages=stage_report(sta, amodel))
         del da
     # image measures of App. B on the reconstruction (GPU kernels)
     phantom = torch.as_tensor(synth.phantom_volume(p), dtype=plan.dtype, device=plan.device)
     msm, _ = time_op(torch, plan, lambda: N.mip(out, 2), a.steps, a.warmup)
+    ten = N.tenenbaum(N.mip(out, 2), normalized=True)
     res["image_measures"] = dict(corrcoef_vs_phantom=round(N.corrcoef(out, phantom), 6),
-                                 tenenbaum_depth_mip=N.tenenbaum(N.mip(out, 2)),
-                                 mip_ms=round(msm, 5))
+                                 tenenbaum_depth_mip_per_pixel=ten, mip_ms=round(msm, 5))
     del phantom
-    if not a.no_lsq:
-        # the step is fixed from a power iteration before the timed region
-        lsq_res = {}
-        for model in ("adjoint", "q"):
-            eta = 0.95 / max(N.power_norm(plan, iters=20, model=model), 1e-300)
-            rhs = g if model == "adjoint" else plan.q(out)
-            N.lsq(plan, rhs, iters=2, eta=eta, model=model)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, losses = N.lsq(plan, rhs, iters=20, eta=eta, model=model)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            lsq_res[model] = dict(ms_per_iteration=round(dt * 1e3 / 20, 4),
-                                  loss_ratio=float(losses[-1] / losses[0]) if losses[0] else None)
-        res["least_squares"] = lsq_res
-    if a.workload == "c2" and not a.no_2d:
-        p2 = synth.config("c8")
-        plan2 = N.Plan(p2.xy, p2.nt, p2.dt, (p2.n1, p2.n2, p2.n3), c=p2.c, h=p2.h, d1=p2.d1,
-                       d2=p2.d2, precision=a.precision)
-        g2 = torch.as_tensor(p2.g, dtype=plan2.dtype, device=plan2.device).contiguous()
-        o2 = torch.empty((p2.n1, p2.n2, p2.n3), dtype=plan2.dtype, device=plan2.device)
-        ms2, _ = time_steps(torch, plan2, g2, o2, a.steps, a.warmup)
-        _, st2 = time_steps(torch, plan2, g2, o2, a.steps, 1, profile=True)
-        res["two_dimensional"] = dict(workload=f"c8: {WORKLOADS['c8']}", ms_per_step=round(ms2, 5),
-                                      value=round(p2.m * p2.nt / (ms2 / 1e3) / 1e6, 2), unit="Mpts/s",
-                                      stages_ms={k: round(v, 5) for k, v in st2.items()})
-        del plan2, g2, o2
     qsample = None
     if not a.no_q:
         # the forward operator Q (initial pressure -> sensor traces) on the
         # reconstructed volume, and its adjoint on the data
         dq = torch.empty((p.m, p.nt), dtype=plan.dtype, device=plan.device)
         vq = torch.empty_like(out)
-        msq, stq = time_op(torch, plan, lambda: plan.q(out, out=dq), a.steps, a.warmup)
+        msq, _ = time_op(torch, plan, lambda: plan.q(out, out=dq), a.steps, a.warmup)
         _, stq = time_op(torch, plan, lambda: plan.q(out, out=dq), a.steps, 1, profile=True)
         msqa, _ = time_op(torch, plan, lambda: plan.q_adjoint(g, out=vq), a.steps, a.warmup)
         _, stqa = time_op(torch, plan, lambda: plan.q_adjoint(g, out=vq), a.steps, 1, profile=True)
@@ -489,20 +646,49 @@ def main(argv=None):
             stages_ms={k: round(v, 5) for k, v in stq.items()},
             adjoint_stages_ms={k: round(v, 5) for k, v in stqa.items()})
         qsample = dq.cpu().numpy()
+        del dq, vq
+    del plan, g, out
+    torch.cuda.empty_cache()
+    if not a.no_lsq:
+        res["least_squares"] = leg_least_squares(torch, N, a)
+    vol_c2 = p2 = None
+    if not a.no_c2 and a.workload != "c2":
+        p2 = synth.config("c2")
+        rec, vol_c2 = leg_precision(torch, N, p2, a.precision, a)
+        rec["workload"] = f"c2: {WORKLOADS['c2']}"
+        rec["note"] = "cache-resident: the 202 MB workspace fits in the 256 MB Infinity Cache"
+        res["cache_resident_c2"] = rec
+    if not a.no_2d:
+        p8 = synth.config("c8")
+        rec, _ = leg_precision(torch, N, p8, a.precision, a)
+        rec["workload"] = f"c8: {WORKLOADS['c8']}"
+        res["two_dimensional"] = rec
+    if not a.no_batch:
+        res["batch_c4"] = leg_batch(torch, N, a, synth.batch_c4(), pool)
+    torch.cuda.empty_cache()
+    res["paper_timings"] = PAPER_TIMINGS
     if not a.no_cpu_baseline:
-        vref, cb = cpu_baseline(p)
-        res["cpu_baseline"] = cb
-        nrm = float(np.linalg.norm(vref))
-        res["rel_l2_vs_oracle"] = float(np.linalg.norm(vol.astype(np.float64) - vref) / nrm)
-        if vol64 is not None:
-            res["fp64_plain"]["rel_l2_vs_oracle"] = float(np.linalg.norm(vol64 - vref) / nrm)
-        if volkb is not None:
-            res["kaiser_bessel_w8"]["rel_l2_vs_oracle"] = float(
-                np.linalg.norm(volkb.astype(np.float64) - vref) / nrm)
+        vref, sec = oracle_full(p)
+        threads = blas_threads()
+        res["cpu_baseline"] = dict(
+            value=round(points / sec / 1e6, 4), unit="Mpts/s", cores=threads, kind="oracle",
+            seconds=round(sec, 2), cpu_model=cpu_model(),
+            sample=(f"the whole workload ({p.m} sensors x {p.nt} samples -> {p.n1}x{p.n2}x{p.n3}): "
+                    f"NED as BLAS GEMMs on {threads} threads, NER by Horner's rule (numpy, one "
+                    "thread), numpy ifftn"))
+        res["rel_l2_vs_oracle"] = rel_l2(vol, vref)
+        for key, v in vols.items():
+            res[key]["rel_l2_vs_oracle"] = rel_l2(v, vref)
         if qsample is not None:
             res["forward_model_q"]["sampled_rel_l2_vs_oracle"] = q_sample_error(p, vol, qsample)
+        if vol_c2 is not None:
+            vref2, _ = oracle_full(p2)
+            res["cache_resident_c2"]["rel_l2_vs_oracle"] = rel_l2(vol_c2, vref2)
     else:
         res["cpu_baseline"] = None
+    if pool is not None:
+        pool.close()
+        pool.join()
     print(json.dumps(res), flush=True)
     return 0
 

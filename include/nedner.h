@@ -71,11 +71,21 @@ typedef enum {
   NEDNER_E_STATE = 7         /* plan unusable after an earlier HIP error */
 } nedner_status;
 
+/* Arithmetic of a plan. "Arguments" are the window and phase arguments:
+   the grid coordinates of the sensors (plan time, host), x(j,l) = omega dt
+   ntt/(2 pi) and the phase (N_t/2 theta + omega t0) mod 2 pi (NER kernels). */
 typedef enum {
   NEDNER_FP64 = 0,              /* every step in double */
-  NEDNER_FP32 = 1,              /* float data and arithmetic, double argument reduction */
-  NEDNER_FP32_COMPENSATED = 2,  /* as FP32, spreading sums carried in double registers */
-  NEDNER_FP32_PLAIN = 3         /* float everywhere, arguments included */
+  NEDNER_FP32 = 1,              /* float data, sums and transforms; double arguments */
+  NEDNER_FP32_COMPENSATED = 2,  /* as FP32, with compensated float sums where many terms meet:
+                                   the spreading sums each grid value as two float partial
+                                   sums (the sensors of the first and of the second half of
+                                   its sweep window) joined by an error-free TwoSum, the
+                                   result rounded once; the adjoint gather adds its W row
+                                   sums with Kahan compensation */
+  NEDNER_FP32_PLAIN = 3,        /* float everywhere, arguments included */
+  NEDNER_FP32_WIDE = 4          /* float data; spreading sums, the adjoint gather's row-sum
+                                   merges and the first-axis spreading weights in double */
 } nedner_precision;
 
 /* Element type of the image measures' inputs. */
@@ -161,8 +171,8 @@ typedef struct {
 typedef struct {
   int32_t rows_per_wave;   /* spreading sweep length (rows of the oversampled grid) */
   int32_t time_per_lane;   /* spreading time samples per lane: 1, 2 or 4 */
-  int32_t spread_depth;    /* spreading sweep: 1 = samples staged through LDS in batches,
-                              2 = two-deep register pipeline */
+  int32_t spread_depth;    /* spreading sweep variant: 1 = samples staged through LDS in
+                              batches (the only one; other values are NEDNER_E_ARG) */
   int32_t pass_lines;      /* FFT passes: lines per workgroup (power of two) */
   int32_t pass_threads;    /* FFT passes: threads per workgroup (64..512, multiple of 64) */
   int32_t pass_inplace;    /* FFT passes: in-place (1) or ping-pong (0) transform */
@@ -174,32 +184,70 @@ typedef struct {
    Gaussian window). */
 void nedner_desc_init(nedner_desc* desc);
 
-/* Host-only validation of a descriptor (no HIP call). Returns NEDNER_E_ARG,
-   NEDNER_E_ALIAS, NEDNER_E_UNSUPPORTED or NEDNER_OK. */
+/* Host-only validation of a descriptor (no HIP call): the sizes, steps and
+   flags of the problem statement of Sec. 2 (sensors on the plane, samples at
+   t0 + n dt, voxels a + i d) and the aliasing bound max |omega| dt < pi of the
+   time sampling (eq. (1) evaluated at the frequencies of eq. (5)). Returns
+   NEDNER_E_ARG, NEDNER_E_ALIAS, NEDNER_E_UNSUPPORTED or NEDNER_OK. */
 nedner_status nedner_validate(const nedner_desc* desc);
 
-/* Host-only: validate and report the sizes the plan would use. */
+/* Host-only: validate and report in *info the sizes the plan would use
+   (oversampled grid, list entries, workspace bytes). No HIP call. */
 nedner_status nedner_query(const nedner_desc* desc, nedner_info* info);
 
-/* Build a plan on `device`: FP64 sensor geometry, window weights, spreading
-   lists, deconvolution and twiddle tables; uploads them on `stream`. */
+/* Build a plan on `device` for the operator of eq. (5) (Sec. 2) evaluated by
+   the NEDNER-NUFFT of Sec. 3: every sensor's grid coordinate is split into a
+   cell and a fraction in FP64 and its window weights are tabulated (the
+   "nearest integers" of the NED step, eq. (10)); the per-column spreading
+   lists, the deconvolution tables 1/phihat of eqs. (8) and (10) and the
+   twiddle tables are built and uploaded. `desc` and its host arrays xy
+   ([m][2] double) and h ([m] double or NULL) are read during the call only.
+   `stream` is accepted for symmetry and not used (uploads are synchronous).
+   On success *plan owns the device tables until nedner_destroy; the
+   workspace is still to be set. Errors: the statuses of nedner_validate,
+   NEDNER_E_OOM (host or device allocation), NEDNER_E_HIP (device selection
+   or upload); *plan is left untouched on failure. */
 nedner_status nedner_plan_create(const nedner_desc* desc, int device, void* stream,
                                  nedner_plan* plan);
 
-/* Batched plan: `count` independent problems run together by the *_many calls. */
+/* Batched plan: `count` independent problems (descs[0..count-1], one
+   precision, window and window width; sizes and sensors may differ) run
+   together by the *_many calls, one persistent launch per pipeline stage.
+   Errors as nedner_plan_create, NEDNER_E_ARG for mixed precision or window. */
 nedner_status nedner_plan_create_many(const nedner_desc* descs, int count, int device,
                                       void* stream, nedner_plan* plan);
 
 nedner_status nedner_plan_info(nedner_plan plan, nedner_info* info);
 nedner_status nedner_workspace_size(nedner_plan plan, size_t* bytes);
-/* Attach a device workspace of at least nedner_workspace_size bytes (256-byte aligned). */
+/* Attach a device workspace of at least nedner_workspace_size bytes (256-byte
+   aligned), owned by the caller, on the plan's device. It must outlive every
+   enqueued execute and must not serve two executes in flight. NULL detaches.
+   NEDNER_E_WORKSPACE when smaller than needed, NEDNER_E_ARG when misaligned. */
 nedner_status nedner_set_workspace(nedner_plan plan, void* d_workspace, size_t bytes);
 
-/* Forward operator: data d_g [m][nt] -> d_out of the requested kind. */
+/* The reconstruction of Sec. 3: eq. (5) evaluated by the NED step (spreading
+   of eq. (10), lateral FFT, deconvolution), the NER step (time FFT and the
+   interpolation of eq. (8) at omega = c sign(kz)|K|, with the weight of
+   eq. (1)) and the closing inverse 3D FFT. d_g: device [m][nt] data of the
+   plan's type (double for NEDNER_FP64, float otherwise), time fastest.
+   d_out: device output of `kind`: NEDNER_VOLUME_REAL [n1][n2][n3] real,
+   NEDNER_SPECTRUM_COMPLEX [n1][n2][n3] complex in FFT order (no closing
+   inverse FFT), NEDNER_STAGE_GRID the spread grid [sigma n1][sigma n2][nt]
+   (no workspace needed). Both buffers belong to the caller; d_out is written
+   completely. Asynchronous on `stream` (a HIP stream of the plan's device,
+   NULL = default). Errors (nothing is launched): NEDNER_E_ARG (NULL plan or
+   pointer, unknown kind, batched plan), NEDNER_E_WORKSPACE (no workspace or
+   too small), NEDNER_E_STATE (after an earlier HIP error); NEDNER_E_HIP when a
+   launch fails (the plan then accepts only nedner_destroy). */
 nedner_status nedner_execute(nedner_plan plan, const void* d_g, void* d_out, int kind,
                              void* stream);
 
-/* Transpose: d_in of the given kind (VOLUME_REAL or STAGE_GRID) -> data d_g [m][nt]. */
+/* The exact transpose of nedner_execute for the real Euclidean inner
+   products on data and volume (it is not in the paper; it makes the
+   reconstruction usable as a differentiable operator): d_in of `kind`
+   (NEDNER_VOLUME_REAL [n1][n2][n3] or NEDNER_STAGE_GRID, the transpose of the
+   spreading alone) -> d_g [m][nt]. Types, ownership, stream and errors as for
+   nedner_execute; NEDNER_SPECTRUM_COMPLEX is NEDNER_E_UNSUPPORTED. */
 nedner_status nedner_execute_adjoint(nedner_plan plan, const void* d_in, int kind, void* d_g,
                                      void* stream);
 
@@ -227,10 +275,26 @@ nedner_status nedner_execute_q(nedner_plan plan, const void* d_v, void* d_g, voi
    workspace and errors as nedner_execute_q. */
 nedner_status nedner_execute_q_adjoint(nedner_plan plan, const void* d_g, void* d_v, void* stream);
 
-/* Batched forward: arrays of `count` device pointers (see plan_create_many). */
+/* Testing hook for the error path: puts the plan into the state a failed
+   HIP call leaves (as if a HIP call of the plan had returned `code`, which
+   must not be hipSuccess) and returns NEDNER_E_HIP with that call's message
+   in nedner_last_error. Launches nothing and touches no device memory.
+   Afterwards every execute, tuning and profiling call on the plan returns
+   NEDNER_E_STATE; nedner_destroy still releases it. NULL plan: NEDNER_E_ARG. */
+nedner_status nedner_debug_inject_hip_error(nedner_plan plan, int code);
+
+/* Batched forward (the reconstruction of nedner_execute for every problem
+   of a plan_create_many plan, one persistent launch per stage over all of
+   them): host arrays of `count` device pointers, d_g[i] the [m_i][nt_i] data
+   and d_out[i] the [n1_i][n2_i][n3_i] volume of problem i. Only
+   NEDNER_VOLUME_REAL. Each problem's result is bitwise equal to its own
+   single-problem plan's. Errors as nedner_execute. */
 nedner_status nedner_execute_many(nedner_plan plan, const void* const* d_g,
                                   void* const* d_out, int kind, void* stream);
 
+/* Release a plan and its device tables (freed with hipFree, which waits for
+   the device's pending work). The caller's workspace and buffers are not
+   touched. NULL is accepted. */
 nedner_status nedner_destroy(nedner_plan plan);
 
 /* ---- image measures (App. B) and projections: no plan needed ----------- */
@@ -263,6 +327,15 @@ nedner_status nedner_corrcoef(const void* d_a, const void* d_b, const unsigned c
 nedner_status nedner_tenenbaum(const void* d_img, int64_t rows, int64_t cols, int64_t r0, int64_t r1,
                                int64_t c0, int64_t c1, int dtype, double* d_result, void* d_work,
                                size_t work_bytes, void* stream);
+
+/* The normalised Tenenbaum measure App. B reports (after eqs. (12)-(13)):
+   the sum of nedner_tenenbaum divided by N, the number of elements of the
+   image it is taken over, here the rectangle [r0, r1) x [c0, c1) as given
+   (0 for an empty rectangle). Arguments, workspace and errors as for
+   nedner_tenenbaum. */
+nedner_status nedner_tenenbaum_mean(const void* d_img, int64_t rows, int64_t cols, int64_t r0, int64_t r1,
+                                    int64_t c0, int64_t c1, int dtype, double* d_result, void* d_work,
+                                    size_t work_bytes, void* stream);
 
 /* Current launch shape of a plan (of its first problem for a batch). */
 nedner_status nedner_get_tuning(nedner_plan plan, nedner_tuning* tuning);

@@ -49,9 +49,9 @@ import numpy as np
 
 __all__ = ["Geometry", "geometry", "mode_numbers", "wavenumbers", "omega",
            "weight", "ned", "ner", "spectrum", "volume_from_spectrum",
-           "forward", "adjoint", "brute_spectrum", "brute_volume",
+           "forward", "adjoint", "adjoint_at", "brute_spectrum", "brute_volume",
            "brute_matrix", "spectrum_at", "trace", "trace_adjoint",
-           "brute_trace", "corrcoef", "tenenbaum", "mip"]
+           "brute_trace", "corrcoef", "tenenbaum", "tenenbaum_mean", "mip"]
 
 # Memory cap for one block of the exponential matrix (complex128 entries).
 _BLOCK_ENTRIES = 1 << 24
@@ -271,6 +271,33 @@ def adjoint(v, xy, h, geo: Geometry) -> np.ndarray:
     return s[:, None] * out
 
 
+def adjoint_at(v, xy, h, geo: Geometry, time_idx) -> np.ndarray:
+    """The adjoint's output at chosen times only: (A* v)[m, n] for every sensor
+    of `xy` (a subset of a workload's sensors, with their h) and each index n
+    of `time_idx`, for workloads whose whole adjoint is too large to evaluate.
+
+    The sums of `adjoint` restricted to those (m, n): V = DFT_3(v)/(N1 N2 N3),
+    Q = (dt/d3) W V, R(j, n) = sum_l Q(j,l) exp(+i omega(j,l) t_n) with the
+    exact exponential at each listed t_n, then
+    h_m/(d1 d2) Re sum_j exp(+i k.(y_m - a)) R(j, n). Returns (M_sub, len(time_idx)).
+    """
+    v = np.asarray(v, dtype=np.float64)
+    n_all = geo.n1 * geo.n2 * geo.n3
+    Q = (geo.dt / geo.d3) * weight(geo) * (np.fft.fftn(v) / n_all)
+    w = omega(geo)
+    xy = np.asarray(xy, dtype=np.float64)
+    s = np.asarray(h, dtype=np.float64) / (geo.d1 * geo.d2)
+    e1, e2 = _lateral_factors(xy, geo)          # exp(-i k y), (N1, M) and (N2, M)
+    idx = np.asarray(time_idx, dtype=np.int64).ravel()
+    out = np.empty((xy.shape[0], idx.size))
+    for i, n in enumerate(idx):
+        t = geo.t0 + float(n) * geo.dt
+        R = (Q * np.exp(1j * w * t)).sum(axis=2)  # (N1, N2)
+        # sum_j exp(+i k.y) R(j) = sum_{j1, j2} conj(e1)[j1, m] R[j1, j2] conj(e2)[j2, m]
+        out[:, i] = np.real(np.einsum("am,ab,bm->m", np.conj(e1), R, np.conj(e2)))
+    return s[:, None] * out
+
+
 def _abs_k(geo: Geometry) -> np.ndarray:
     """|K(j,l)| on the (N1, N2, N3) mode grid, FFT order."""
     k1, k2, kz = wavenumbers(geo)
@@ -465,6 +492,19 @@ def tenenbaum(img, rect=None) -> float:
             gy = float(np.sum(g.T * patch))
             total += gx * gx + gy * gy
     return total
+
+
+def tenenbaum_mean(img, rect=None) -> float:
+    """The normalised Tenenbaum measure of App. B: F / N, with F the sum of
+    `tenenbaum` and N the number of elements of the image it is taken over
+    (the rectangle rect = (r0, r1, c0, c1) as given, the whole image without
+    it), so that the measure does not grow with the image size.
+    """
+    u = np.asarray(img)
+    rows, cols = u.shape
+    r0, r1, c0, c1 = (0, rows, 0, cols) if rect is None else rect
+    count = max(r1 - r0, 0) * max(c1 - c0, 0)
+    return tenenbaum(img, rect) / count if count else 0.0
 
 
 def mip(vol, axis: int) -> np.ndarray:

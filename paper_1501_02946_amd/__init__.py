@@ -27,7 +27,7 @@ __all__ = ["Plan", "BatchPlan", "NednerRecon", "NednerAdjoint", "NednerQ", "Nedn
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libnedner.so")
 
-PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "fp32_plain": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "fp32_plain": 3, "fp32w": 4}
 KINDS = {"volume": 0, "spectrum": 1, "grid": 2}
 FLAGS = {"allow_alias": 1, "wrap": 2, "deterministic": 4, "no_autotune": 8, "equispaced": 16}
 WINDOWS = {"gaussian": 0, "kaiser_bessel": 1, "kb": 1}
@@ -80,7 +80,8 @@ EXPORTS = ["nedner_desc_init", "nedner_validate", "nedner_query", "nedner_plan_c
            "nedner_last_error", "nedner_version", "nedner_profile_begin", "nedner_profile_end",
            "nedner_get_tuning", "nedner_set_tuning", "nedner_autotune", "nedner_execute_q",
            "nedner_execute_q_adjoint", "nedner_metrics_workspace_size", "nedner_mip",
-           "nedner_corrcoef", "nedner_tenenbaum"]
+           "nedner_corrcoef", "nedner_tenenbaum", "nedner_tenenbaum_mean",
+           "nedner_debug_inject_hip_error"]
 
 
 def _declare(L):
@@ -105,8 +106,10 @@ def _declare(L):
     L.nedner_mip.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
     L.nedner_corrcoef.argtypes = [vp, vp, vp, i64, i32, vp, vp, sz, vp]
     L.nedner_tenenbaum.argtypes = [vp, i64, i64, i64, i64, i64, i64, i32, vp, vp, sz, vp]
+    L.nedner_tenenbaum_mean.argtypes = [vp, i64, i64, i64, i64, i64, i64, i32, vp, vp, sz, vp]
     L.nedner_execute_q_adjoint.argtypes = [vp, vp, vp, vp]
     L.nedner_destroy.argtypes = [vp]
+    L.nedner_debug_inject_hip_error.argtypes = [vp, i32]
     L.nedner_status_string.argtypes = [i32]
     L.nedner_status_string.restype = ctypes.c_char_p
     L.nedner_last_error.argtypes = []
@@ -196,7 +199,8 @@ class Plan:
     samples `nt` at t0 + n dt, sound speed `c`, output `volume` = (N1, N2, N3)
     with voxel (i1, i2, i3) at (a1 + i1 d1, a2 + i2 d2, i3 d3); d1, d2 default
     to a unit aperture, d3 to c nt dt / N3. `precision` is one of "fp64",
-    "fp32", "fp32c" (compensated spreading) or "fp32_plain"; `window` is
+    "fp32", "fp32c" (compensated float sums), "fp32_plain" (float arguments
+    too) or "fp32w" (double spreading sums); `window` is
     "gaussian" (default) or "kaiser_bessel" with `w` taps per axis.
     """
 
@@ -567,13 +571,16 @@ def power_norm(plan: Plan, iters: int = 10, seed: int = 0, model: str = "adjoint
 
 
 def lsq(plan: Plan, g, iters: int = 20, eta: float | None = None, x0=None, callback=None,
-        model: str = "adjoint"):
+        model: str = "adjoint", sync: bool = True):
     """Projected gradient descent on J(x) = 1/2 ||M x - g||^2 with x >= 0.
 
     M is the adjoint A* of the reconstruction (model="adjoint") or the forward
     operator Q of the wave equation (model="q"). The gradient M* (M x - g) is
     taken by autograd through NednerAdjoint or NednerQ, so each iteration runs
-    the operator and its transpose once. Returns (x, losses).
+    the operator and its transpose once. Returns (x, losses): with sync the
+    losses are floats read after every iteration (a host synchronisation each);
+    without it, and without a callback, they stay 0-d device tensors until the
+    caller reads them, so the iterations run back to back on the stream.
     """
     torch = plan._torch
     if model not in ("adjoint", "q"):
@@ -590,7 +597,7 @@ def lsq(plan: Plan, g, iters: int = 20, eta: float | None = None, x0=None, callb
         r = op.apply(x, plan) - g
         loss = 0.5 * torch.sum(r * r)
         (grad,) = torch.autograd.grad(loss, x)
-        losses.append(float(loss.detach()))
+        losses.append(float(loss.detach()) if (sync or callback is not None) else loss.detach())
         with torch.no_grad():
             x = torch.clamp(x - eta * grad, min=0.0)
         if callback is not None:
@@ -653,9 +660,11 @@ def corrcoef(a, b, mask=None) -> float:
     return float(res.item())
 
 
-def tenenbaum(img, rect=None) -> float:
+def tenenbaum(img, rect=None, normalized=False) -> float:
     """Tenenbaum sharpness of a device image (rows, cols) (App. B, eqs. (12)-(13))
-    over the pixels of rect = (r0, r1, c0, c1) with a full 3x3 neighbourhood."""
+    over the pixels of rect = (r0, r1, c0, c1) with a full 3x3 neighbourhood;
+    with normalized, the paper's F / N, N the element count of the rectangle
+    (of the whole image without rect)."""
     import torch
     if img.dim() != 2 or not img.is_cuda:
         raise ValueError("a 2-D device tensor is expected")
@@ -663,9 +672,10 @@ def tenenbaum(img, rect=None) -> float:
     rows, cols = u.shape
     r0, r1, c0, c1 = (0, rows, 0, cols) if rect is None else rect
     work, res = _metric_buffers(u)
+    fn = lib().nedner_tenenbaum_mean if normalized else lib().nedner_tenenbaum
     with torch.cuda.device(u.device):
-        _check(lib().nedner_tenenbaum(ctypes.c_void_p(u.data_ptr()), rows, cols, r0, r1, c0, c1,
-                                      _dtype_code(u), ctypes.c_void_p(res.data_ptr()),
-                                      ctypes.c_void_p(work.data_ptr()), work.numel(),
-                                      ctypes.c_void_p(torch.cuda.current_stream(u.device).cuda_stream)))
+        _check(fn(ctypes.c_void_p(u.data_ptr()), rows, cols, r0, r1, c0, c1,
+                  _dtype_code(u), ctypes.c_void_p(res.data_ptr()),
+                  ctypes.c_void_p(work.data_ptr()), work.numel(),
+                  ctypes.c_void_p(torch.cuda.current_stream(u.device).cuda_stream)))
     return float(res.item())

@@ -21,8 +21,9 @@ BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libnedner.so")
 
-SOURCES = ["capi.cpp", "k_spread.hip", "k_passes.hip", "k_column.hip", "k_column_f64.hip",
-           "k_column_f32.hip", "k_column_f32p.hip", "k_metrics.hip"]
+SOURCES = ["capi.cpp", "k_spread.hip", "k_spread_f64.hip", "k_spread_f32.hip", "k_spread_f32c.hip",
+           "k_spread_f32w.hip", "k_passes.hip", "k_column.hip", "k_column_f64.hip", "k_column_f32.hip",
+           "k_column_f32p.hip", "k_metrics.hip"]
 
 ARCH = os.environ.get("NEDNER_OFFLOAD_ARCH", "gfx950")
 

@@ -129,9 +129,9 @@ double window_phihat(const Derived& v, double k, double n) {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t real_size(int prec) { return prec == NEDNER_FP64 ? 8 : 4; }
-// Tuning overrides read at plan creation: NEDNER_SPREAD="depth,wide" sets the
-// spreading sweep (1: samples staged through LDS, 2: two-deep register
-// pipeline) and, for FP32C, 8-byte weights (0 or 1).
+// Tuning override read at plan creation: NEDNER_SPREAD="1,wide" keeps the
+// one spreading sweep (samples staged through LDS) and sets, for FP32W,
+// 8-byte first-axis weights (wide = 1, the default) or 4-byte ones (0).
 struct SpreadOpt {
   int pd = 1, wide = 1;
 };
@@ -139,16 +139,13 @@ SpreadOpt spread_opt() {
   SpreadOpt o;
   if (const char* e = getenv("NEDNER_SPREAD")) {
     int a = 0, b = 0;
-    if (sscanf(e, "%d,%d", &a, &b) == 2 && (a == 1 || a == 2)) {
-      o.pd = a;
-      o.wide = b != 0;
-    }
+    if (sscanf(e, "%d,%d", &a, &b) == 2 && a == 1) o.wide = b != 0;
   }
   return o;
 }
 
 size_t weight_size(int prec) {
-  return prec == NEDNER_FP64 || (prec == NEDNER_FP32_COMPENSATED && spread_opt().wide) ? 8 : 4;
+  return prec == NEDNER_FP64 || (prec == NEDNER_FP32_WIDE && spread_opt().wide) ? 8 : 4;
 }
 
 // Workspace: buffer 0 holds U, then G, then Z2; buffer 1 holds V, then Z1.
@@ -205,7 +202,7 @@ nedner_status validate_impl(const nedner_desc* d, Derived* out) {
   if (!finite(d->d1) || !finite(d->d2) || !(d->d1 > 0) || !(d->d2 > 0))
     return fail(NEDNER_E_ARG, "d1, d2 must be finite and > 0");
   if (!finite(d->d3) || d->d3 < 0) return fail(NEDNER_E_ARG, "d3 must be finite and >= 0");
-  if (d->prec < 0 || d->prec > 3) return fail(NEDNER_E_ARG, "unknown precision");
+  if (d->prec < 0 || d->prec > 4) return fail(NEDNER_E_ARG, "unknown precision");
   if (d->w < 2 || d->w > 16 || (d->w % 2)) return fail(NEDNER_E_ARG, "w must be even and in [2, 16]");
   if (!finite(d->sigma) || !(d->sigma > 1.0)) return fail(NEDNER_E_ARG, "sigma must be finite and > 1");
   if (!finite(d->tau_scale) || !(d->tau_scale > 0)) return fail(NEDNER_E_ARG, "tau_scale must be finite and > 0");
@@ -288,10 +285,11 @@ nedner_status validate_impl(const nedner_desc* d, Derived* out) {
   v.TT = TT;
   v.nchunk = int((d->nt + 64 * TT - 1) / (64 * TT));
   int S = d->rows_per_wave;
-  // sweeps of 32 rows (at least 2W): shorter sweeps waste the W-1 warm-up
-  // cells, longer ones leave too few wavefronts to hide the load latency
-  // (measured on the 128^2 x 512 and 256^2 x 1024 workloads)
-  if (S == 0) S = std::max(32, 2 * v.W);
+  // mean sweep length n1/4, at least 4W: shorter sweeps spend much of their
+  // work on the W-1 warm-up cells, longer ones leave too few wavefronts to
+  // hide the load latency (measured on the 128^2 x 512 and 256^2 x 1024
+  // workloads; the autotuner refines it)
+  if (S == 0) S = int(std::max<long>(4L * v.W, v.n1 / 4));
   S = int(std::min<long>(S, v.n1));
   v.S = S;
   v.nseg = int((v.n1 + S - 1) / S);
@@ -310,7 +308,9 @@ struct Geometry {
   std::vector<double> w1u;      // [M][W] first-axis window values without s_m
   std::vector<int> ent_m;
   std::vector<double> ent_w2;
-  std::vector<int> cellbeg;     // [n2 * nseg][CB]
+  std::vector<int> cellbeg;     // per segment, per column of its group: list offsets per sweep cell
+  std::vector<int> segd;        // [segments][4]: column group, first row S0, end row S1, offset of
+                                // the group's first column's table in cellbeg
   std::vector<int> node;        // equispaced: [n1 * n2] sensor at each node, -1 where none
   std::vector<double> s;        // equispaced: [M] h_m / (d1 d2)
 };
@@ -403,33 +403,103 @@ void build_geometry(const nedner_desc& d, const Derived& v, Geometry& G) {
     }
     for (auto& t : taps) percol[t.first].push_back({G.cell[2 * m], int(m), t.second});
   }
-  G.cellbeg.assign((size_t)v.n2 * v.nseg * v.CB, 0);
-  std::vector<int> rowstart(v.n1 + 1);
-  std::vector<E> sorted;
+  // each column's entries sorted by first-axis cell (counting sort, stable:
+  // sensor order within a cell)
+  std::vector<std::vector<int>> rowstart(v.n2);
+  std::vector<std::vector<E>> sorted(v.n2);
+  int64_t total = 0;
   for (long q2 = 0; q2 < v.n2; ++q2) {
     auto& L2v = percol[q2];
-    std::fill(rowstart.begin(), rowstart.end(), 0);
-    for (auto& e : L2v) rowstart[e.c1 + 1]++;
-    for (long r = 0; r < v.n1; ++r) rowstart[r + 1] += rowstart[r];
-    sorted.resize(L2v.size());
-    {
-      std::vector<int> pos(rowstart.begin(), rowstart.end() - 1);
-      for (auto& e : L2v) sorted[pos[e.c1]++] = e;  // stable: sensor order within a cell
+    auto& rs = rowstart[q2];
+    rs.assign(v.n1 + 1, 0);
+    for (auto& e : L2v) rs[e.c1 + 1]++;
+    for (long r = 0; r < v.n1; ++r) rs[r + 1] += rs[r];
+    sorted[q2].resize(L2v.size());
+    std::vector<int> pos(rs.begin(), rs.end() - 1);
+    for (auto& e : L2v) sorted[q2][pos[e.c1]++] = e;
+    total += int64_t(L2v.size());
+    std::vector<E>().swap(L2v);
+  }
+  // Sweep segments, per group of four columns (one workgroup): a segment of
+  // rows [S0, S1) sweeps the cell rows S0 - W/2 .. S1 + W/2 - 2, and costs the
+  // entries of those cell rows over the group's columns. Segments are cut so
+  // that each costs about what a segment of S rows costs at the mean density,
+  // W-1 overlap rows included: dense parts of the aperture get short
+  // segments, sparse ones long ones, and every wavefront of the launch does
+  // about the same work. Segments keep at least min(W, S) rows (shorter ones
+  // would mostly sweep overlap) and at most 4 S.
+  // NEDNER_SEGMENTS="cut,order" overrides the defaults (cut 0: balanced as
+  // above, 1: fixed S rows; order 0: the segments of a group consecutive,
+  // 1: by first row, then group).
+  int seg_cut = 0, seg_order = 0;
+  if (const char* e = getenv("NEDNER_SEGMENTS")) {
+    int a = 0, b = 0;
+    if (sscanf(e, "%d,%d", &a, &b) == 2) {
+      seg_cut = a;
+      seg_order = b;
     }
-    for (int s = 0; s < v.nseg; ++s) {
-      const int S0 = s * v.S, S1 = std::min<int>(S0 + v.S, int(v.n1));
-      const int Vstart = S0 - W / 2, Vend = S1 + W / 2 - 2;
-      int* cb = &G.cellbeg[((size_t)q2 * v.nseg + s) * v.CB];
-      for (int V = Vstart; V <= Vend; ++V) {
-        cb[V - Vstart] = int(G.ent_m.size());
-        const int c = int(((long)V % v.n1 + v.n1) % v.n1);
-        for (int i = rowstart[c]; i < rowstart[c + 1]; ++i) {
-          G.ent_m.push_back(sorted[i].m);
-          G.ent_w2.push_back(sorted[i].w2);
-        }
+  }
+  const long ncg = (v.n2 + 3) / 4;
+  const double avg = double(total) / (double(ncg) * double(v.n1));
+  const double target = seg_cut == 1 ? 1e300 : avg * double(v.S + W - 1);
+  const long minlen = seg_cut == 1 ? std::min<long>(v.S, v.n1) : std::max<long>(1, std::min<long>(W, v.S));
+  const long maxlen = seg_cut == 1 ? std::min<long>(v.S, v.n1) : std::min<long>(v.n1, 4L * v.S);
+  std::vector<double> cost(v.n1);
+  auto rowcost = [&](long V) { return cost[size_t(((V % v.n1) + v.n1) % v.n1)]; };
+  G.segd.clear();
+  G.cellbeg.clear();
+  for (long cg = 0; cg < ncg; ++cg) {
+    std::fill(cost.begin(), cost.end(), 0.0);
+    for (long w = 0; w < 4 && 4 * cg + w < v.n2; ++w) {
+      const auto& rs = rowstart[4 * cg + w];
+      for (long r = 0; r < v.n1; ++r) cost[r] += double(rs[r + 1] - rs[r]);
+    }
+    long S0 = 0;
+    while (S0 < v.n1) {
+      long S1 = std::min<long>(S0 + minlen, v.n1);
+      double c = 0.0;
+      for (long V = S0 - W / 2; V <= S1 + W / 2 - 2; ++V) c += rowcost(V);
+      while (S1 < v.n1 && S1 - S0 < maxlen) {
+        const double add = rowcost(S1 + W / 2 - 1);
+        if (c + add > target) break;
+        c += add;
+        ++S1;
       }
-      cb[Vend - Vstart + 1] = int(G.ent_m.size());
+      G.segd.insert(G.segd.end(), {int(cg), int(S0), int(S1), int(G.cellbeg.size())});
+      const long len = S1 - S0 + W;  // offsets of cell rows Vstart..Vend, then the end
+      for (long w = 0; w < 4; ++w) {
+        const long q2 = 4 * cg + w;
+        const size_t base = G.cellbeg.size();
+        G.cellbeg.resize(base + size_t(len), int(G.ent_m.size()));
+        if (q2 >= v.n2) continue;
+        const auto& rs = rowstart[q2];
+        const auto& so = sorted[q2];
+        const long Vstart = S0 - W / 2, Vend = S1 + W / 2 - 2;
+        for (long V = Vstart; V <= Vend; ++V) {
+          G.cellbeg[base + size_t(V - Vstart)] = int(G.ent_m.size());
+          const long c1 = ((V % v.n1) + v.n1) % v.n1;
+          for (int i = rs[c1]; i < rs[c1 + 1]; ++i) {
+            G.ent_m.push_back(so[i].m);
+            G.ent_w2.push_back(so[i].w2);
+          }
+        }
+        G.cellbeg[base + size_t(Vend - Vstart + 1)] = int(G.ent_m.size());
+      }
+      S0 = S1;
     }
+  }
+  if (seg_order == 1) {
+    const size_t ns = G.segd.size() / 4;
+    std::vector<size_t> idx(ns);
+    for (size_t i = 0; i < ns; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+      return G.segd[4 * a + 1] != G.segd[4 * b + 1] ? G.segd[4 * a + 1] < G.segd[4 * b + 1]
+                                                     : G.segd[4 * a] < G.segd[4 * b];
+    });
+    std::vector<int> sorted_d(G.segd.size());
+    for (size_t i = 0; i < ns; ++i)
+      for (int k = 0; k < 4; ++k) sorted_d[4 * i + k] = G.segd[4 * idx[i] + k];
+    G.segd.swap(sorted_d);
   }
 }
 
@@ -470,6 +540,8 @@ struct ListTables {
   const int* em = nullptr;
   const void* ew = nullptr;
   const int* cb = nullptr;
+  const int* segd = nullptr;
+  int nsegt = 0;
 };
 constexpr int LIST_PAD = 16;
 
@@ -483,6 +555,8 @@ ListTables upload_lists(const Geometry& G, bool wide, DevAlloc& L) {
   t.em = static_cast<const int*>(L.upload(em));
   t.ew = wide ? L.upload(ew) : L.upload_as<float>(ew);
   t.cb = static_cast<const int*>(L.upload(G.cellbeg));
+  t.segd = static_cast<const int*>(L.upload(G.segd));
+  t.nsegt = int(G.segd.size() / 4);
   return t;
 }
 
@@ -528,13 +602,14 @@ struct nedner_plan_s {
 
 namespace {
 
-void fill_info(const nedner_desc& d, const Derived& v, int64_t entries, nedner_info* info) {
+void fill_info(const nedner_desc& d, const Derived& v, int64_t entries, int64_t segments,
+               int64_t cb_entries, nedner_info* info) {
   std::memset(info, 0, sizeof(*info));
   info->n1_os = int(v.n1);
   info->n2_os = int(v.n2);
   info->nt_os = int(v.ntt);
   info->columns = v.J1 * v.K2;
-  info->segments = v.nseg;
+  info->segments = int(segments);
   info->rows_per_wave = v.S;
   info->time_per_lane = v.TT;
   size_t off1;
@@ -542,7 +617,7 @@ void fill_info(const nedner_desc& d, const Derived& v, int64_t entries, nedner_i
   const size_t ws = weight_size(d.prec), rs = real_size(d.prec);
   info->list_entries = entries;
   info->table_bytes = (size_t)d.m * (2 * v.W * ws + 8) + entries * (4 + ws) +
-                      (size_t)v.n2 * v.nseg * v.CB * 4 + (v.J1 + v.K2 + d.nt) * rs +
+                      size_t(cb_entries) * 4 + size_t(segments) * 16 + (v.J1 + v.K2 + d.nt) * rs +
                       2 * rs * (v.n1 + v.n2 + v.ntt + d.n1 + d.n2 + d.n3);
   info->beta = v.beta;
   info->max_abs_theta = v.max_theta;
@@ -578,50 +653,11 @@ nedner_status hip_fail(nedner_plan p, hipError_t e, const char* where) {
   return fail(NEDNER_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-// Sweep length when the descriptor leaves it open: the number of segments
-// whose spreading launch makes the fewest rounds of resident workgroups times
-// rows per sweep (each wave sweeps S + W - 1 cell rows), S in [2W, 256].
-// A launch whose last round is nearly empty runs its tail at a fraction of the
-// chip, so whole rounds of long sweeps beat many short ones.
-int balanced_rows(const Derived& v, long resident) {
-  const long base = (v.n2 + 3) / 4 * (long)v.nchunk;
-  int best_s = v.S;
-  double best = 1e300;
-  for (long nseg = 1; nseg <= v.n1; ++nseg) {
-    const long S = (v.n1 + nseg - 1) / nseg;
-    if (S > 256) continue;
-    if (S < 2 * v.W) break;
-    const long rounds = (base * nseg + resident - 1) / resident;
-    const double cost = double(rounds) * double(S + v.W - 1);
-    if (cost < best) {
-      best = cost;
-      best_s = int(S);
-    }
-  }
-  return best_s;
-}
-
 nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* out) {
   Derived v;
   nedner_status st = validate_impl(desc_in, &v);
   if (st != NEDNER_OK) return st;
   nedner_desc dd = *desc_in;
-  if (dd.rows_per_wave == 0) {
-    DeviceGuard g0(device);
-    int cus = 0;
-    if (g0.ok() && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
-        cus > 0) {
-      KP q{};
-      q.prec = dd.prec;
-      q.W = v.W;
-      q.TT = v.TT;
-      q.spread_pd = spread_opt().pd;
-      q.wide_w = dd.prec == NEDNER_FP32_COMPENSATED && spread_opt().wide;
-      dd.rows_per_wave = balanced_rows(v, long(nedner::spread_blocks_per_cu(q)) * cus);
-      st = validate_impl(&dd, &v);
-      if (st != NEDNER_OK) return st;
-    }
-  }
   const nedner_desc* desc = &dd;
   nedner_plan p = new (std::nothrow) nedner_plan_s();
   if (!p) return fail(NEDNER_E_OOM, "host allocation failed");
@@ -641,7 +677,8 @@ nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* ou
     delete p;
     return fail(NEDNER_E_UNSUPPORTED, "too many spreading list entries");
   }
-  fill_info(*desc, v, int64_t(G.ent_m.size()), &p->info);
+  fill_info(*desc, v, int64_t(G.ent_m.size()), int64_t(G.segd.size() / 4), int64_t(G.cellbeg.size()),
+            &p->info);
   workspace_layout(*desc, v, &p->off1, &p->need_ws);
 
   DeviceGuard guard(device);
@@ -709,7 +746,7 @@ nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* ou
   }
   const SpreadOpt so = spread_opt();
   k.spread_pd = so.pd;
-  k.wide_w = desc->prec == NEDNER_FP32_COMPENSATED && so.wide;
+  k.wide_w = desc->prec == NEDNER_FP32_WIDE && so.wide;
   const bool wide = desc->prec == NEDNER_FP64 || k.wide_w;
   const bool dbl = desc->prec == NEDNER_FP64;
   k.w1 = wide ? A.upload(G.w1) : A.upload_as<float>(G.w1);
@@ -744,6 +781,8 @@ nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* ou
     k.ent_m = t.em;
     k.ent_w2 = t.ew;
     k.cellbeg = t.cb;
+    k.segd = t.segd;
+    k.nsegt = t.nsegt;
     p->list_allocs = Lst.ptrs;
     if (Lst.err != hipSuccess && A.err == hipSuccess) A.err = Lst.err;
   }
@@ -910,7 +949,7 @@ size_t stage_blocks(const KP& k, int stage, int cpw) {
   const int cs = k.prec == NEDNER_FP64 ? 16 : 8;
   switch (stage) {
     case nedner::ST_SPREAD: {
-      const long G = ceil_div(k.n2, 4) * k.nseg * k.nchunk;
+      const long G = (long)k.nsegt * k.nchunk;
       return size_t(8 * ceil_div(G, 8));
     }
     case nedner::ST_LAT_A: return size_t(ceil_div(k.Nt / 2, nedner::pass_lines_for(k, k.n2, cs)) * k.n1);
@@ -1088,8 +1127,9 @@ nedner_status execute_many_impl(nedner_plan plan, const void* const* d_g, void* 
 
 // ---------------------------------------------------------------- reshaping and tuning
 
-// Rebuild the spreading lists of a single-problem plan for sweeps of S rows,
-// TT samples per lane and pipeline depth PD. Weights and workspace do not change.
+// Rebuild the spreading lists of a single-problem plan for sweeps of S rows
+// and TT samples per lane (PD, the sweep variant, is 1: samples staged
+// through LDS). Weights and workspace do not change.
 nedner_status set_spread_shape(nedner_plan p, int S, int TT, int PD) {
   nedner_desc d = p->desc;
   d.xy = p->hxy.data();
@@ -1120,6 +1160,8 @@ nedner_status set_spread_shape(nedner_plan p, int S, int TT, int PD) {
   k.ent_m = t.em;
   k.ent_w2 = t.ew;
   k.cellbeg = t.cb;
+  k.segd = t.segd;
+  k.nsegt = t.nsegt;
   k.TT = v.TT;
   k.S = v.S;
   k.nseg = v.nseg;
@@ -1129,7 +1171,7 @@ nedner_status set_spread_shape(nedner_plan p, int S, int TT, int PD) {
   p->v = v;
   p->desc.rows_per_wave = S;
   p->desc.time_per_lane = TT;
-  p->info.segments = v.nseg;
+  p->info.segments = t.nsegt;
   p->info.rows_per_wave = v.S;
   p->info.time_per_lane = v.TT;
   p->info.list_entries = int64_t(G.ent_m.size());
@@ -1217,20 +1259,18 @@ nedner_status tune_spread(nedner_plan p, const void* d_g, void* U, hipStream_t s
     tts.push_back(fixed_tt);
   else
     for (int tt : {4, 2, 1})
-      if (Nt % tt == 0 && (tt == 1 || Nt >= 32 * tt)) tts.push_back(tt);
-  // sweep lengths that split the n1 rows into nseg equal segments
+      if (Nt % tt == 0 && (tt == 1 || Nt >= 32 * tt) && (tt > 1 || Nt < 128)) tts.push_back(tt);
+  // mean sweep lengths on a geometric ladder from 2W to the grid
   std::vector<int> ss;
-  for (int nseg = 1; nseg <= n1; ++nseg) {
-    const int S = (n1 + nseg - 1) / nseg;
-    if (S < 2 * W) break;
-    if (S <= 256 && (ss.empty() || ss.back() != S)) ss.push_back(S);
-  }
-  if (ss.empty()) ss.push_back(n1);
+  for (int S : {24, 32, 48, 64, 96, 128, 171, 256})
+    if (S >= 2 * W && S <= n1) ss.push_back(S);
+  const int top = std::min(n1, 256);
+  if (ss.empty() || ss.back() < top) ss.push_back(top);
   int bS = p->kp.S, bT = p->kp.TT, bP = p->kp.spread_pd;
   double best = 1e300;
   for (int tt : tts)
     for (int S : ss)
-      for (int pd : {1, 2}) {
+      for (int pd : {1}) {
         nedner_status st = set_spread_shape(p, S, tt, pd);
         if (st != NEDNER_OK) return st;
         double ms = 0;
@@ -1342,7 +1382,7 @@ nedner_status autotune_batch(nedner_plan bp, hipStream_t s, nedner_tuning* out) 
   double best = 1e300;
   int bS = 64, bP = 1;
   nedner_status st = NEDNER_OK;
-  for (int pd : {1, 2}) {
+  for (int pd : {1}) {
     for (int S : {32, 64, 128, 256}) {
       st = shape(S, pd);
       if (st != NEDNER_OK) break;
@@ -1403,6 +1443,26 @@ void destroy_one(nedner_plan p) {
 
 }  // namespace
 
+namespace {
+nedner_status tenenbaum_impl(const void* d_img, int64_t rows, int64_t cols, int64_t r0, int64_t r1, int64_t c0,
+                             int64_t c1, int dtype, bool mean, double* d_result, void* d_work, size_t work_bytes,
+                             void* stream) {
+  if (!d_img || !d_result || !d_work) return fail(NEDNER_E_ARG, "NULL device pointer");
+  if (rows < 1 || cols < 1) return fail(NEDNER_E_ARG, "image sizes must be positive");
+  if (r0 < 0 || c0 < 0 || r1 > rows || c1 > cols || r0 > r1 || c0 > c1)
+    return fail(NEDNER_E_ARG, "rectangle outside the image");
+  if (dtype != NEDNER_DTYPE_F32 && dtype != NEDNER_DTYPE_F64) return fail(NEDNER_E_ARG, "unknown dtype");
+  if (work_bytes < nedner::METRICS_WORK_BYTES)
+    return fail(NEDNER_E_WORKSPACE, "workspace smaller than nedner_metrics_workspace_size");
+  const double count = double(r1 - r0) * double(c1 - c0);
+  const double scale = mean ? (count > 0.0 ? 1.0 / count : 0.0) : 1.0;
+  const hipError_t e = nedner::launch_tenenbaum(d_img, long(rows), long(cols), long(r0), long(r1), long(c0),
+                                                long(c1), dtype == NEDNER_DTYPE_F64, scale, d_result, d_work,
+                                                static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NEDNER_OK : fail(NEDNER_E_HIP, std::string("tenenbaum: ") + hipGetErrorString(e));
+}
+}  // namespace
+
 extern "C" {
 
 void nedner_desc_init(nedner_desc* d) {
@@ -1431,7 +1491,7 @@ nedner_status nedner_query(const nedner_desc* desc, nedner_info* info) {
   } catch (const std::bad_alloc&) {
     return fail(NEDNER_E_OOM, "host allocation failed");
   }
-  fill_info(*desc, v, int64_t(G.ent_m.size()), info);
+  fill_info(*desc, v, int64_t(G.ent_m.size()), int64_t(G.segd.size() / 4), int64_t(G.cellbeg.size()), info);
   return NEDNER_OK;
 }
 
@@ -1529,6 +1589,7 @@ nedner_status nedner_execute_many(nedner_plan plan, const void* const* d_g, void
 
 nedner_status nedner_profile_begin(nedner_plan plan, int max_runs) {
   if (!plan) return fail(NEDNER_E_ARG, "plan is NULL");
+  if (plan->broken) return fail(NEDNER_E_STATE, "plan is unusable after an earlier HIP error");
   if (max_runs < 1 || max_runs > 100000) return fail(NEDNER_E_ARG, "max_runs must be in [1, 100000]");
   DeviceGuard guard(plan->device);
   if (!guard.ok()) return fail(NEDNER_E_HIP, "cannot select the plan's device");
@@ -1588,7 +1649,7 @@ nedner_status nedner_set_tuning(nedner_plan plan, const nedner_tuning* t) {
   if (!plan || !t) return fail(NEDNER_E_ARG, "NULL argument");
   if (!plan->subs.empty()) return fail(NEDNER_E_UNSUPPORTED, "set_tuning applies to single-problem plans");
   if (plan->broken) return fail(NEDNER_E_STATE, "plan is unusable after an earlier HIP error");
-  if (!pass_shape_ok(t->pass_lines, t->pass_threads) || (t->spread_depth != 1 && t->spread_depth != 2) ||
+  if (!pass_shape_ok(t->pass_lines, t->pass_threads) || t->spread_depth != 1 ||
       t->rows_per_wave < 1)
     return fail(NEDNER_E_ARG, "invalid tuning");
   nedner_status st = set_spread_shape(plan, t->rows_per_wave, t->time_per_lane, t->spread_depth);
@@ -1633,20 +1694,24 @@ nedner_status nedner_corrcoef(const void* d_a, const void* d_b, const unsigned c
   return e == hipSuccess ? NEDNER_OK : fail(NEDNER_E_HIP, std::string("corrcoef: ") + hipGetErrorString(e));
 }
 
+
 nedner_status nedner_tenenbaum(const void* d_img, int64_t rows, int64_t cols, int64_t r0, int64_t r1,
                                int64_t c0, int64_t c1, int dtype, double* d_result, void* d_work,
                                size_t work_bytes, void* stream) {
-  if (!d_img || !d_result || !d_work) return fail(NEDNER_E_ARG, "NULL device pointer");
-  if (rows < 1 || cols < 1) return fail(NEDNER_E_ARG, "image sizes must be positive");
-  if (r0 < 0 || c0 < 0 || r1 > rows || c1 > cols || r0 > r1 || c0 > c1)
-    return fail(NEDNER_E_ARG, "rectangle outside the image");
-  if (dtype != NEDNER_DTYPE_F32 && dtype != NEDNER_DTYPE_F64) return fail(NEDNER_E_ARG, "unknown dtype");
-  if (work_bytes < nedner::METRICS_WORK_BYTES)
-    return fail(NEDNER_E_WORKSPACE, "workspace smaller than nedner_metrics_workspace_size");
-  const hipError_t e = nedner::launch_tenenbaum(d_img, long(rows), long(cols), long(r0), long(r1), long(c0),
-                                                long(c1), dtype == NEDNER_DTYPE_F64, d_result, d_work,
-                                                static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? NEDNER_OK : fail(NEDNER_E_HIP, std::string("tenenbaum: ") + hipGetErrorString(e));
+  return tenenbaum_impl(d_img, rows, cols, r0, r1, c0, c1, dtype, false, d_result, d_work, work_bytes, stream);
+}
+
+nedner_status nedner_tenenbaum_mean(const void* d_img, int64_t rows, int64_t cols, int64_t r0, int64_t r1,
+                                    int64_t c0, int64_t c1, int dtype, double* d_result, void* d_work,
+                                    size_t work_bytes, void* stream) {
+  return tenenbaum_impl(d_img, rows, cols, r0, r1, c0, c1, dtype, true, d_result, d_work, work_bytes, stream);
+}
+
+nedner_status nedner_debug_inject_hip_error(nedner_plan plan, int code) {
+  if (!plan) return fail(NEDNER_E_ARG, "plan is NULL");
+  if (code == int(hipSuccess)) return fail(NEDNER_E_ARG, "an injected error code must not be hipSuccess");
+  for (nedner_plan sp : plan->subs) sp->broken = true;
+  return hip_fail(plan, static_cast<hipError_t>(code), "injected by nedner_debug_inject_hip_error");
 }
 
 nedner_status nedner_destroy(nedner_plan plan) {

@@ -1,4 +1,4 @@
-// NER column kernels instantiated for FP32 data with FP64 frequency and phase arguments (fp32, fp32c).
+// NER column kernels instantiated for FP32 data with FP64 frequency and phase arguments (fp32, fp32c, fp32w).
 #include "k_column_impl.hpp"
 
 namespace nedner {

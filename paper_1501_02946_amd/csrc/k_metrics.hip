@@ -5,7 +5,8 @@
 //              moments, so that a large mean does not cancel the covariance;
 //   tenenbaum: sum over the pixels of a rectangle whose 3x3 neighbourhood lies
 //              in the image of (g * U)^2 + (g^T * U)^2, g the Sobel kernel
-//              (eqs. (12)-(13));
+//              (eqs. (12)-(13)), optionally divided by the rectangle's element
+//              count (the normalised measure App. B reports);
 //   mip      : maximum along one axis of an (N1, N2, N3) volume, depth fastest.
 //
 // The sums accumulate in double. Every reduction runs on a fixed grid of
@@ -130,13 +131,15 @@ __global__ __launch_bounds__(MET_THREADS) void k_tenenbaum(const T* __restrict__
   if (threadIdx.x == 0) work[blockIdx.x] = sh[0];
 }
 
-__global__ __launch_bounds__(MET_THREADS) void k_sum_finish(const double* __restrict__ work,
+// The sum of the workgroups' partial sums times `scale` (1, or 1/N for the
+// normalised measure).
+__global__ __launch_bounds__(MET_THREADS) void k_sum_finish(const double* __restrict__ work, double scale,
                                                             double* __restrict__ result) {
   __shared__ double sh[MET_THREADS];
   double v[1] = {0.0};
   for (int j = threadIdx.x; j < MET_BLOCKS; j += MET_THREADS) v[0] += work[j];
   block_sum<1>(v, sh);
-  if (threadIdx.x == 0) *result = sh[0];
+  if (threadIdx.x == 0) *result = sh[0] * scale;
 }
 
 // Maximum over the first (axis 0) or second (axis 1) index: one thread per
@@ -214,7 +217,7 @@ hipError_t launch_corrcoef(const void* a, const void* b, const unsigned char* ma
 }
 
 hipError_t launch_tenenbaum(const void* img, long rows, long cols, long r0, long r1, long c0, long c1, bool dbl,
-                            double* result, void* work, hipStream_t s) {
+                            double scale, double* result, void* work, hipStream_t s) {
   r0 = r0 > 1 ? r0 : 1;
   c0 = c0 > 1 ? c0 : 1;
   r1 = r1 < rows - 1 ? r1 : rows - 1;
@@ -226,7 +229,7 @@ hipError_t launch_tenenbaum(const void* img, long rows, long cols, long r0, long
   else
     hipLaunchKernelGGL(k_tenenbaum<float>, dim3(MET_BLOCKS), dim3(MET_THREADS), 0, s,
                        static_cast<const float*>(img), cols, r0, r1, c0, c1, w);
-  hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(MET_THREADS), 0, s, w, result);
+  hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(MET_THREADS), 0, s, w, scale, result);
   return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@
 
 namespace nedner {
 
-enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP32C = 2, PREC_FP32P = 3 };
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP32C = 2, PREC_FP32P = 3, PREC_FP32W = 4 };
 
 struct KP {
   // ---- sizes -------------------------------------------------------------
@@ -24,13 +24,14 @@ struct KP {
   int J1;         // first-axis columns kept: N1 + 1 (both Nyquist representatives)
   int W;          // window taps per dimension
   int TT;         // time samples per lane in spreading
-  int S;          // rows per spreading sweep segment
-  int nseg;       // sweep segments along the first axis
-  int CB;         // stride of the per-(column, segment) cell offset table: S + W
+  int S;          // mean rows per spreading sweep segment (the tuning parameter)
+  int nseg;       // ceil(n1 / S)
+  int CB;         // S + W
+  int nsegt;      // sweep segments of all column groups (entries of segd)
   int nchunk;     // time chunks of 64*TT samples
   int prec;       // Prec
-  int spread_pd;  // spreading sweep: 1 = samples staged through LDS, 2 = two-deep register pipeline
-  int wide_w;     // FP32C: 8-byte first-axis weights (fetched at use) instead of 4-byte
+  int spread_pd;  // spreading sweep variant: 1 = samples staged through LDS (the only one)
+  int wide_w;     // FP32W: 8-byte first-axis weights (fetched at use) instead of 4-byte
   int pass_lines; // FFT passes: lines per workgroup (power of two, upper bound)
   int pass_threads; // FFT passes: threads per workgroup (multiple of 64, <= 512)
   int pass_ip;    // FFT passes: in-place (1) or ping-pong (0) transform
@@ -57,7 +58,10 @@ struct KP {
   const int* cell;     // [M][2] (c1, c2)
   const int* ent_m;    // spreading list: sensor of each entry
   const void* ent_w2;  // spreading list: second-axis weight of each entry
-  const int* cellbeg;  // [n2 * nseg][CB] list offsets per sweep cell
+  const int* cellbeg;  // list offsets per sweep cell: per segment, the tables of the four
+                       // columns of its group, each S1 - S0 + W entries (cells Vstart..Vend, end)
+  const int* segd;     // [nsegt][4] sweep segments: column group, S0, S1, offset of the first
+                       // column's table in cellbeg (segments of a group consecutive)
   const int* node;     // equispaced: [n1 * n2] sensor at each node, -1 where none
   const int* gorder;   // [M] the sensors in the order the adjoint gather takes them: by tiles
                        // of 4 x 4 grid cells, so that consecutive sensors are neighbours
@@ -112,7 +116,7 @@ hipError_t launch_spread(const KP& p, const void* g, void* U, hipStream_t s);
 // Equispaced sensors: U at each node = s_m g[m] (zero where no sensor), and its transpose.
 hipError_t launch_place(const KP& p, const void* g, void* U, hipStream_t s);
 hipError_t launch_place_adj(const KP& p, const void* U, void* g, hipStream_t s);
-// Workgroups of the forward spreading kernel (prec, W, TT, spread_pd, wide_w of p) per CU.
+// Workgroups of the forward spreading kernel (prec, W, TT, wide_w of p) per CU.
 int spread_blocks_per_cu(const KP& p);
 
 // Image measures and projections (k_metrics.hip); the reductions use a
@@ -122,7 +126,7 @@ hipError_t launch_mip(const void* vol, int n1, int n2, int n3, int axis, bool db
 hipError_t launch_corrcoef(const void* a, const void* b, const unsigned char* mask, long n, bool dbl,
                            double* result, void* work, hipStream_t s);
 hipError_t launch_tenenbaum(const void* img, long rows, long cols, long r0, long r1, long c0, long c1, bool dbl,
-                            double* result, void* work, hipStream_t s);
+                            double scale, double* result, void* work, hipStream_t s);
 hipError_t launch_gather(const KP& p, const void* U, void* g, hipStream_t s);
 hipError_t launch_lat_a(const KP& p, const void* U, void* V, hipStream_t s);
 hipError_t launch_lat_b(const KP& p, const void* V, void* G, hipStream_t s);

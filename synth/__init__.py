@@ -98,10 +98,18 @@ def phantom_volume(p: "Problem") -> np.ndarray:
     x2 = p.a2 + d2 * np.arange(p.n2)
     z = d3 * np.arange(p.n3)
     out = np.zeros((p.n1, p.n2, p.n3))
+
+    def span(lo, step, n, c, R):
+        # voxel indices whose coordinate lies within [c - R, c + R], one wider each side
+        i0 = max(int(np.floor((c - R - lo) / step)) - 1, 0)
+        i1 = min(int(np.ceil((c + R - lo) / step)) + 2, n)
+        return slice(i0, max(i0, i1))
+
     for (bx, by, bz, R, p0) in p.balls:
-        r2 = ((x1[:, None, None] - bx) ** 2 + (x2[None, :, None] - by) ** 2
-              + (z[None, None, :] - bz) ** 2)
-        out += np.where(r2 <= R * R, p0, 0.0)
+        s1, s2, s3 = span(p.a1, d1, p.n1, bx, R), span(p.a2, d2, p.n2, by, R), span(0.0, d3, p.n3, bz, R)
+        r2 = ((x1[s1, None, None] - bx) ** 2 + (x2[None, s2, None] - by) ** 2
+              + (z[None, None, s3] - bz) ** 2)
+        out[s1, s2, s3] += np.where(r2 <= R * R, p0, 0.0)
     return out
 
 

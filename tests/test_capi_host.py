@@ -118,23 +118,41 @@ def test_flags_lift_checks():
     assert _validate(xy=np.array([[1.25, -0.5]]), flags=["wrap"])[0] == 0
 
 
-def _expected_entries(p, info, W=12):
-    """Count (sensor, column, sweep cell) list entries from their definition."""
+def _expected_segments_and_entries(p, info, W=12):
+    """Sweep segments and (sensor, column, sweep cell) list entries from their
+    definition: per group of four columns of the oversampled grid, segments
+    of rows [S0, S1) cut in order so that each costs (entries in the cell rows
+    S0 - W/2 .. S1 + W/2 - 2 over the group's columns) at most what S + W - 1
+    rows cost at the mean density, but keeps at least min(W, S) rows and at
+    most 4 S."""
     n1, n2 = info["n1_os"], info["n2_os"]
-    S, nseg = info["rows_per_wave"], info["segments"]
+    S = info["rows_per_wave"]
     u1 = n1 * (p.xy[:, 0] - p.a1) / (p.n1 * p.d1)
     u2 = n2 * (p.xy[:, 1] - p.a2) / (p.n2 * p.d2)
     c1 = np.floor(u1).astype(int) % n1
     c2 = np.floor(u2).astype(int) % n2
-    total = 0
-    for s in range(nseg):
-        s0, s1 = s * S, min(s * S + S, n1)
-        cells = np.arange(s0 - W // 2, s1 + W // 2 - 1) % n1
-        mult = np.bincount(cells, minlength=n1)
-        for m in range(p.m):
-            cols = len(set(((c2[m] + np.arange(W) - W // 2 + 1) % n2).tolist()))
-            total += cols * mult[c1[m]]
-    return total
+    # per column: entries per first-axis cell (a sensor enters each distinct column its taps reach)
+    count = np.zeros((n2, n1), dtype=np.int64)
+    for m in range(p.m):
+        for col in set(((c2[m] + np.arange(W) - W // 2 + 1) % n2).tolist()):
+            count[col, c1[m]] += 1
+    ncg = (n2 + 3) // 4
+    target = count.sum() / (ncg * n1) * (S + W - 1)
+    minlen, maxlen = max(1, min(W, S)), min(n1, 4 * S)
+    segments = entries = 0
+    for cg in range(ncg):
+        cost = count[4 * cg:4 * cg + 4].sum(axis=0)
+        s0 = 0
+        while s0 < n1:
+            s1 = min(s0 + minlen, n1)
+            c = sum(cost[v % n1] for v in range(s0 - W // 2, s1 + W // 2 - 1))
+            while s1 < n1 and s1 - s0 < maxlen and c + cost[(s1 + W // 2 - 1) % n1] <= target:
+                c += cost[(s1 + W // 2 - 1) % n1]
+                s1 += 1
+            segments += 1
+            entries += int(c)
+            s0 = s1
+    return segments, entries
 
 
 @pytest.mark.parametrize("name", ["c1", "c5sub"])
@@ -158,8 +176,7 @@ def test_query_sizes(name):
     assert abs(info["beta"] - beta) < 1e-15
     k = math.pi * np.array([p.n1 / (p.n1 * p.d1), p.n2 / (p.n2 * p.d2), 1.0 / p.d3])
     assert abs(info["max_abs_theta"] - p.c * p.dt * np.linalg.norm(k)) < 1e-12
-    assert info["segments"] == math.ceil(2 * p.n1 / info["rows_per_wave"])
-    assert info["list_entries"] == _expected_entries(p, info)
+    assert (info["segments"], info["list_entries"]) == _expected_segments_and_entries(p, info)
     info64 = N.query(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), h=p.h, precision="fp64")
     assert info64["workspace_bytes"] == up(2 * max(U, G, Z2)) + up(2 * max(V, Z1))
 
@@ -234,3 +251,8 @@ def test_batch_descriptor_checks_before_any_device_work():
     assert L.nedner_get_tuning(None, ctypes.byref(t)) == E_ARG
     assert L.nedner_set_tuning(None, ctypes.byref(t)) == E_ARG
     assert L.nedner_autotune(None, None, None, ctypes.byref(t)) == E_ARG
+
+
+def test_injected_hip_error_needs_a_plan():
+    L = N.lib()
+    assert L.nedner_debug_inject_hip_error(None, 1) == E_ARG

@@ -69,6 +69,9 @@ def test_tenenbaum(torch_gpu, dtype, shape, rect):
     got = N.tenenbaum(torch.as_tensor(u, device="cuda"), rect)
     want = O.tenenbaum(u, rect)
     assert abs(got - want) <= 1e-12 * max(abs(want), 1e-300)
+    got_mean = N.tenenbaum(torch.as_tensor(u, device="cuda"), rect, normalized=True)
+    want_mean = O.tenenbaum_mean(u, rect)
+    assert abs(got_mean - want_mean) <= 1e-12 * max(abs(want_mean), 1e-300)
 
 
 def test_tenenbaum_ramp_large(torch_gpu):

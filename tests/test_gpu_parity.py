@@ -51,7 +51,7 @@ def test_spread_grid_matches_oracle_ned(torch_gpu):
     assert err <= TOL
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32", "fp32w"])
 def test_c1_volume_and_spectrum(torch_gpu, prec):
     p = synth.config("c1")
     geo, F, v = _oracle(p)
@@ -70,7 +70,7 @@ def test_c1_volume_and_spectrum(torch_gpu, prec):
     dict(seed=3, s=9, nt=48, n=(12, 20, 24), d3=0.03, jitter=0.49),
     dict(seed=4, s=16, nt=64, n=(16, 16, 40)),
 ])
-@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32w"])
 def test_ragged_cases(torch_gpu, case, prec):
     p = small_problem(**case)
     geo, F, v = _oracle(p)
@@ -153,7 +153,7 @@ def test_c2_full_volume(torch_gpu):
     """The benchmark workload (128x128 sensors, 512 samples, 128x128x256), full oracle."""
     p = synth.config("c2")
     geo, F, v = _oracle(p)
-    for prec in ("fp32c", "fp32", "fp64"):
+    for prec in ("fp32c", "fp32", "fp32w", "fp64"):
         plan = make_plan(p, prec)
         vg = plan(to_dev(p.g, plan)).cpu().numpy()
         err = rel_l2(vg, v)

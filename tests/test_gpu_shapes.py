@@ -1,6 +1,7 @@
 """Every launch shape the autotuner can pick gives the same operator: parity
-with the oracle for each sweep variant, samples per lane, sweep length and
-FFT-pass form (set through the tuning interface), forward and adjoint."""
+with the oracle for each number of samples per lane, sweep length and
+FFT-pass form (set through the tuning interface), forward and adjoint, in
+each precision."""
 import itertools
 
 import numpy as np
@@ -24,10 +25,10 @@ def case():
     return p, geo, v, y, O.adjoint(y, p.xy, p.h, geo)
 
 
-SHAPES = list(itertools.product([1, 2, 4], [1, 2], [24, 40], [(16, 512, 1), (8, 256, 1), (16, 256, 0)]))
+SHAPES = list(itertools.product([1, 2, 4], [1], [24, 40], [(16, 512, 1), (8, 256, 1), (16, 256, 0)]))
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32", "fp32w"])
 def test_every_shape(case, prec):
     p, geo, v, y, aty = case
     plan = make_plan(p, prec)

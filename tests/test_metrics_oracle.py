@@ -36,6 +36,23 @@ def test_tenenbaum_of_a_ramp(alpha, beta):
     assert abs(got - (4 - 1) * (12 - 3) * 64.0 * (alpha ** 2 + beta ** 2)) <= 1e-9
 
 
+@pytest.mark.parametrize("rows,cols", [(9, 13), (30, 7), (64, 64)])
+def test_tenenbaum_mean_of_a_ramp_is_size_free(rows, cols):
+    """App. B normalises the measure by the element count N of the image: for
+    a ramp F = (rows - 2)(cols - 2) 64 (alpha^2 + beta^2) and N = rows cols, so
+    F / N tends to 64 (alpha^2 + beta^2) as the image grows."""
+    alpha, beta = 0.7, -1.3
+    r, c = np.meshgrid(np.arange(rows), np.arange(cols), indexing="ij")
+    u = alpha * r + beta * c
+    per_pixel = 64.0 * (alpha ** 2 + beta ** 2)
+    want = (rows - 2) * (cols - 2) * per_pixel / (rows * cols)
+    assert abs(O.tenenbaum_mean(u) - want) <= 1e-12 * want
+    # over a rectangle N counts the rectangle's elements, border pixels included
+    got = O.tenenbaum_mean(u, rect=(0, 4, 3, cols))
+    assert abs(got - (4 - 1) * (cols - 1 - 3) * per_pixel / (4 * (cols - 3))) <= 1e-9
+    assert O.tenenbaum_mean(u, rect=(2, 2, 0, cols)) == 0.0
+
+
 def test_tenenbaum_of_a_point():
     u = np.zeros((11, 10))
     u[5, 4] = 1.0

@@ -66,6 +66,18 @@ def test_adjoint_is_transpose_of_brute_matrix():
     assert np.abs(fw.ravel() - A @ g.ravel()).max() <= 1e-12 * max(1.0, np.abs(fw).max())
 
 
+def test_adjoint_at_chosen_times_is_transpose_of_brute_matrix():
+    """The restricted adjoint (chosen sensors and times, for full-size checks)
+    against the transpose of the brute-force matrix."""
+    xy, h, g, geo = _tiny_case(8, m=5, nt=6, n=(4, 2, 4))
+    A = O.brute_matrix(xy, h, geo)
+    v = _rng(9).normal(size=(geo.n1, geo.n2, geo.n3))
+    at = (A.T @ v.ravel()).reshape(xy.shape[0], geo.nt)
+    sel, tid = np.array([4, 0, 2]), np.array([5, 0, 3])
+    got = O.adjoint_at(v, xy[sel], h[sel], geo, tid)
+    assert np.abs(got - at[np.ix_(sel, tid)]).max() <= 1e-12 * np.abs(A).max() * v.size
+
+
 def test_adjoint_identity_medium():
     p = synth.config("c5sub")
     geo = O.geometry(**p.geometry_kwargs())
