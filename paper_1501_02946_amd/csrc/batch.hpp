@@ -58,6 +58,7 @@ hipError_t launch_pass_many(const KP& p0, int stage, const BatchProb* bp, const 
 hipError_t launch_column_many(const KP& p0, const BatchProb* bp, const WorkList& wl, int cpw,
                               size_t smem, hipStream_t s);
 size_t column_wave_bytes_host(const KP& p);
+int column_wpc_host(const KP& p);
 size_t column_shared_bytes_host(const KP& p);
 
 }  // namespace nedner

@@ -1012,12 +1012,14 @@ nedner_status create_batch(const nedner_desc* descs, int count, int device, nedn
     wave_max = std::max(wave_max, nedner::column_wave_bytes_host(sp->kp));
     shared_max = std::max(shared_max, nedner::column_shared_bytes_host(sp->kp));
   }
+  // columns per workgroup (of wpc wavefronts each, at most 512 threads)
+  const int wpc = nedner::column_wpc_host(bp->kp0);
   int best = 1;
   size_t best_waves = 0;
-  for (int cw = 1; cw <= 8; ++cw) {
+  for (int cw = 1; cw * wpc <= 8; ++cw) {
     const size_t wg = shared_max + cw * wave_max;
     if (wg > 160 * 1024) break;
-    const size_t waves = cw * ((160 * 1024) / wg);
+    const size_t waves = cw * wpc * ((160 * 1024) / wg);
     if (waves > best_waves) {
       best_waves = waves;
       best = cw;

@@ -131,7 +131,31 @@ __device__ __forceinline__ LPoint<R, ARGS64> lpoint(const KP& p, double a, int l
   LPoint<R, ARGS64> o;
   const double l2 = double(l) * double(l);
   R rr;
-  if constexpr (ARGS64) {
+  if constexpr (ARGS64 && sizeof(R) == 4) {
+    // float data: |K| in double from a float reciprocal square root and one
+    // Newton step (relative error ~1e-14, far below what x needs), x and the
+    // phase reduced in double; the weight, which only scales a float value,
+    // in float; sin and cos of the reduced phase (in turns) by the hardware
+    const double s2 = a + l2 * p.bz;
+    const float y = s2 > 0.0 ? __builtin_amdgcn_rsqf(float(s2)) : 0.0f;
+    double kk = s2 * double(y);
+    kk = fma(0.5 * double(y), fma(-kk, kk, s2), kk);
+    const double x = (l > 0 ? 1.0 : (l < 0 ? -1.0 : 0.0)) * p.cdtnt * kk;
+    const double fl = floor(x);
+    o.q0 = int(fl);
+    o.fr = R(x - fl);
+    double r = x * p.phase_p;
+    r -= rint(r);
+    const float rf = float(r);
+    float w = 0.0f;
+    if (l != 0)
+      w = float(p.two_c * sqrt(p.bz)) * fabsf(float(l)) * __builtin_amdgcn_rcpf(float(kk));
+    else if (a == 0.0)
+      w = float(p.two_c);
+    o.wgt = R(w * float(scale));
+    o.ph = cpx<R>{__builtin_amdgcn_cosf(rf), -__builtin_amdgcn_sinf(rf)};
+    return o;
+  } else if constexpr (ARGS64) {
     const double kk = sqrt(a + l2 * p.bz);
     const double x = (l > 0 ? 1.0 : (l < 0 ? -1.0 : 0.0)) * p.cdtnt * kk;
     const double fl = floor(x);
@@ -206,9 +230,9 @@ __device__ __forceinline__ double x_lateral(const KP& p, double a) {
     return double(float(p.cdtnt) * sqrtf(float(a)));
 }
 
-// LDS of one workgroup: the two twiddle tables, shared, then per wavefront
-// (one column each) the transform buffer and, unless the forward kernel keeps
-// its per-l values in registers, the per-l arrays.
+// LDS of one workgroup: the two twiddle tables, shared, then per column the
+// transform buffer and, unless the forward kernel keeps its per-l values in
+// registers, the per-l arrays.
 template <typename R>
 struct ColSmem {
   cpx<R>* twt;  // ntt twiddles
@@ -220,11 +244,18 @@ struct ColSmem {
   int* st;      // ntt + 2 (adjoint): number of points below each grid cell
 };
 
-// The forward kernel holds the N3 + 1 values of a column in registers, NL_REG
-// per lane, when they fit (N3 + 1 <= 64 NL_REG); the transform buffer then
-// is all the LDS a column needs, which doubles the columns resident per CU.
+// The forward kernel holds the N3 + 1 values of a column in registers when
+// they fit (N3 + 1 <= 64 NL_REG, NL_REG per lane with one wavefront per
+// column, fewer with more); the transform buffer then is all the LDS a
+// column needs, which doubles the columns resident per CU.
 constexpr int NL_REG = 9;
 __host__ __device__ inline bool col_fl_in_regs(int N3) { return N3 + 1 <= 64 * NL_REG; }
+
+// Wavefronts per column: one for transforms up to 512 points (a wavefront
+// holds them in 8 points per lane), four above, so that a column's stages
+// run on 256 threads and a CU holds more wavefronts than it has columns'
+// worth of LDS. Shared by the single and the batched launches.
+__host__ __device__ inline int column_wpc(int ntt, int N3) { return (ntt > N3 ? ntt : N3) > 512 ? 4 : 1; }
 
 template <typename R>
 __host__ __device__ inline size_t col_wave_bytes(int ntt, int N3, bool adj) {
@@ -242,12 +273,12 @@ __host__ __device__ inline size_t col_shared_bytes(int ntt, int N3) {
 }
 
 template <typename R>
-__device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int wave, bool adj) {
+__device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int column, bool adj) {
   ColSmem<R> s;
   const int nbuf = (p.ntt > p.N3 ? p.ntt : p.N3) + COL_EXT;
   s.twt = reinterpret_cast<cpx<R>*>(smem);
   s.tw3 = s.twt + p.ntt;
-  char* w = smem + col_shared_bytes<R>(p.ntt, p.N3) + (size_t)wave * col_wave_bytes<R>(p.ntt, p.N3, adj);
+  char* w = smem + col_shared_bytes<R>(p.ntt, p.N3) + (size_t)column * col_wave_bytes<R>(p.ntt, p.N3, adj);
   s.a = reinterpret_cast<cpx<R>*>(w);
   s.fl = s.a + nbuf;
   s.fr = reinterpret_cast<R*>(s.fl + p.N3 + 2);
@@ -256,43 +287,52 @@ __device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int wav
   return s;
 }
 
-// One wavefront per column; a workgroup of CPW wavefronts shares the twiddles.
+// WPC wavefronts per column (CN = 64 WPC threads); a workgroup of CPW columns
+// shares the twiddles. With one wavefront per column a column waits only on
+// its own LDS traffic; with several, every stage ends at a workgroup barrier,
+// which every column of the workgroup reaches: a column past the end of the
+// list, or one the half-spectrum inverse leaves out, runs the same steps on
+// zeros and writes nothing.
 // SPEC: write the full spectrum F (N1, N2, N3) in FFT order instead of Z1.
-template <typename R, int W, bool ARGS64, bool SPEC, int PPT, bool KBW>
+template <typename R, int W, bool ARGS64, bool SPEC, int PPT, bool KBW, int WPC>
 __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const cpx<R>* __restrict__ G,
                                             void* out) {
   extern __shared__ __align__(16) char smem[];
+  constexpr int CN = 64 * WPC;
+  constexpr bool WV = WPC == 1;
+  constexpr int NLW = (NL_REG + WPC - 1) / WPC;
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int ct = tid % CN, cw = tid / CN;
   const int ntt = p.ntt, N3 = p.N3, Nt = p.Nt, h3 = N3 / 2;
-  ColSmem<R> sm = col_carve<R>(smem, p, wave, false);
+  ColSmem<R> sm = col_carve<R>(smem, p, cw, false);
   load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
   load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
   __syncthreads();
-  const int cidx = __builtin_amdgcn_readfirstlane(bx * (nth >> 6) + wave);
-  if (cidx >= ncol) return;
-  const int k2 = cidx / p.J1, je = cidx - k2 * p.J1;
-  const size_t col = cidx;
+  const int cidx = __builtin_amdgcn_readfirstlane(bx * (nth / CN) + cw);
+  const bool live = cidx < ncol;
+  const int cc = live ? cidx : 0;
+  const int k2 = cc / p.J1, je = cc - k2 * p.J1;
+  const size_t col = cc;
   double fac;
   int pol;
   column_policy(je, k2, p.N1, p.N2, fac, pol);
-  if (!SPEC && fac == 0.0) {
+  const bool act = live && (SPEC || fac != 0.0);
+  if (live && !act) {
     cpx<R>* z1 = static_cast<cpx<R>*>(out) + col * N3;
-    for (int i = lane; i < N3; i += 64) z1[i] = cpx<R>{R(0), R(0)};
-    return;
+    for (int i = ct; i < N3; i += CN) z1[i] = cpx<R>{R(0), R(0)};
   }
   const cpx<R>* gc = G + col * Nt;
-  stage_in<(PPT < 16 ? PPT : 16)>(sm.a, ntt, lane, 64, [&](int s) {
+  stage_in<(PPT < 16 ? PPT : 16)>(sm.a, ntt, ct, CN, [&](int s) {
     // slot s holds n' = s (s < ntt/2) or s - ntt; data index n = n' + Nt/2
     const int np = s < ntt / 2 ? s : s - ntt;
     const int n = np + Nt / 2;
-    return (n >= 0 && n < Nt) ? gc[n] : cpx<R>{R(0), R(0)};
+    return (act && n >= 0 && n < Nt) ? gc[n] : cpx<R>{R(0), R(0)};
   });
-  wave_sync();
-  fft_lds_ip<false, R, true, PPT>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, lane, 64);
+  sync_policy<WV>();
+  fft_lds_ip<false, R, WV, PPT>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, ct, CN);
   const cpx<R>* B = sm.a;
-  if (lane < W) sm.a[ntt + lane] = sm.a[lane];
-  wave_sync();
+  if (ct < W) sm.a[ntt + ct] = sm.a[ct];
+  sync_policy<WV>();
   const int j1 = je - p.N1 / 2;
   const double a = double(j1) * double(j1) * p.inv_L1sq + double(k2) * double(k2) * p.inv_L2sq;
   const double scale = SPEC ? p.scale_spec : p.scale_vol;
@@ -308,8 +348,8 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
   for (int k = 0; k < W / 2; ++k) rk[k] = R(exp(-p.beta * (2 * k + 1)));
   const bool chain = p.beta <= 8.0;  // exp(2 beta fr) stays far from overflow
   const R twow = R(2.0 / W);
-  // the value of output li = lane + 64 i, i < NL_REG, when they stay in registers
-  cpx<R> hl[NL_REG];
+  // the value of output li = ct + CN i, i < NLW, when they stay in registers
+  cpx<R> hl[NLW];
   const bool in_regs = col_fl_in_regs(N3);
   // H(x) exp(-i phase) at the point lp
   auto taps = [&](const LPoint<R, ARGS64>& lp) {
@@ -354,27 +394,27 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
   };
   if (in_regs) {
 #pragma unroll
-    for (int i = 0; i < NL_REG; ++i) {
-      const int li = lane + 64 * i;
-      if (64 * i <= N3 && li <= N3) hl[i] = gather(li);
+    for (int i = 0; i < NLW; ++i) {
+      const int li = ct + CN * i;
+      if (CN * i <= N3 && li <= N3) hl[i] = gather(li);
     }
   } else {
-    for (int li = lane; li <= N3; li += 64) sm.fl[li] = gather(li);
+    for (int li = ct; li <= N3; li += CN) sm.fl[li] = gather(li);
   }
   // Q*: the l = 0 value from the two points +-x0
   cpx<R> hz = {R(0), R(0)};
-  if (cosm && lane == 0) {
+  if (cosm && ct == 0) {
     const double x0 = x_lateral<ARGS64>(p, a);
     hz = (taps(lpoint_at<R, ARGS64>(p, x0)) + taps(lpoint_at<R, ARGS64>(p, -x0))) * (R(0.5) * cscale);
   }
-  wave_sync();
+  sync_policy<WV>();
   if constexpr (SPEC) {
     cpx<R>* F = static_cast<cpx<R>*>(out);
     const int N1 = p.N1, N2 = p.N2;
     // columns k2 in [0, N2/2) are written as they are (with N2 = 1 the one
     // row k2 = 0), the others through the Hermitian mirror
-    const bool direct = k2 < (N2 + 1) / 2 && je < N1;
-    const bool mirror = k2 >= 1 && je >= 1;
+    const bool direct = act && k2 < (N2 + 1) / 2 && je < N1;
+    const bool mirror = act && k2 >= 1 && je >= 1;
     const size_t rd = ((size_t)pmodc(j1, N1) * N2 + k2) * N3;
     const size_t rm = ((size_t)pmodc(-j1, N1) * N2 + pmodc(-k2, N2)) * N3;
     auto emit = [&](int li, cpx<R> v) {
@@ -384,12 +424,12 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
     };
     if (in_regs) {
 #pragma unroll
-      for (int i = 0; i < NL_REG; ++i) {
-        const int li = lane + 64 * i;
-        if (64 * i <= N3 && li <= N3) emit(li, hl[i]);
+      for (int i = 0; i < NLW; ++i) {
+        const int li = ct + CN * i;
+        if (CN * i <= N3 && li <= N3) emit(li, hl[i]);
       }
     } else {
-      for (int li = lane; li <= N3; li += 64) emit(li, sm.fl[li]);
+      for (int li = ct; li <= N3; li += CN) emit(li, sm.fl[li]);
     }
   } else {
     // X[slot] for the depth inverse, in the transform buffer (free again):
@@ -404,45 +444,47 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
     };
     if (in_regs) {
 #pragma unroll
-      for (int i = 0; i < NL_REG; ++i) {
-        const int li = lane + 64 * i;
-        if (64 * i <= N3 && li <= N3) place(li, hl[i]);
+      for (int i = 0; i < NLW; ++i) {
+        const int li = ct + CN * i;
+        if (CN * i <= N3 && li <= N3) place(li, hl[i]);
       }
     } else {
-      for (int li = lane; li <= N3; li += 64) place(li, sm.fl[li]);
+      for (int li = ct; li <= N3; li += CN) place(li, sm.fl[li]);
     }
-    wave_sync();
+    sync_policy<WV>();
     if (cosm) {
       // average slot s (l) with slot N3 - s (-l); the Nyquist pair is h3, N3;
       // slot 0 (l = 0) takes the two-point value
-      if (lane == 0) X[0] = hz * f;
-      for (int s = lane + 1; s < h3; s += 64) {
+      if (ct == 0) X[0] = hz * f;
+      for (int s = ct + 1; s < h3; s += CN) {
         const cpx<R> m = (X[s] + X[N3 - s]) * R(0.5);
         X[s] = m;
         X[N3 - s] = m;
       }
-      if (lane == 0) {
+      if (ct == 0) {
         const cpx<R> m = (X[h3] + X[N3]) * R(0.5);
         X[h3] = m;
         X[N3] = m;
       }
-      wave_sync();
+      sync_policy<WV>();
     }
-    if (lane == 0) {
+    if (ct == 0) {
       const cpx<R> lo = X[h3], hi = X[N3];
       X[h3] = pol == 0 ? lo : (pol == 1 ? hi : (lo + hi) * R(0.5));
     }
-    wave_sync();
-    fft_lds_ip<true, R, true, PPT>(X, p.r_N3, 1, 1, 0, sm.tw3, lane, 64);
+    sync_policy<WV>();
+    fft_lds_ip<true, R, WV, PPT>(X, p.r_N3, 1, 1, 0, sm.tw3, ct, CN);
     const cpx<R>* Zr = X;
-    cpx<R>* z1 = static_cast<cpx<R>*>(out) + col * N3;
-    for (int i = lane; i < N3; i += 64) z1[i] = Zr[i];
+    if (act) {
+      cpx<R>* z1 = static_cast<cpx<R>*>(out) + col * N3;
+      for (int i = ct; i < N3; i += CN) z1[i] = Zr[i];
+    }
   }
 }
 
-template <typename R, int W, bool ARGS64, bool SPEC, int PPT, bool KBW>
+template <typename R, int W, bool ARGS64, bool SPEC, int PPT, bool KBW, int WPC>
 __global__ __launch_bounds__(512) void k_column(KP p, int ncol, const cpx<R>* __restrict__ G, void* out) {
-  column_body<R, W, ARGS64, SPEC, PPT, KBW>(p, ncol, blockIdx.x, G, out);
+  column_body<R, W, ARGS64, SPEC, PPT, KBW, WPC>(p, ncol, blockIdx.x, G, out);
 }
 
 // First index i in [lo, hi) with q[i] >= v (q non-decreasing).
@@ -457,34 +499,39 @@ __device__ __forceinline__ int lower_bound_i(const int* q, int lo, int hi, int v
   return lo;
 }
 
-template <typename R, int W, bool ARGS64, int PPT, bool KBW>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW, int WPC>
 __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap, int bx,
                                                 const cpx<R>* __restrict__ Z1, cpx<R>* __restrict__ G) {
   extern __shared__ __align__(16) char smem[];
+  constexpr int CN = 64 * WPC;
+  constexpr bool WV = WPC == 1;
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int ct = tid % CN, cw = tid / CN;
   const int ntt = p.ntt, N3 = p.N3, Nt = p.Nt, h3 = N3 / 2;
-  ColSmem<R> sm = col_carve<R>(smem, p, wave, true);
+  ColSmem<R> sm = col_carve<R>(smem, p, cw, true);
   load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
   load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
   __syncthreads();
-  const int cidx = __builtin_amdgcn_readfirstlane(bx * (nth >> 6) + wave);
-  if (cidx >= ncol) return;
-  const int k2 = cidx / p.J1, je = cidx - k2 * p.J1;
-  const size_t col = cidx;
+  // a column past the end of the list, or one the half-spectrum inverse
+  // leaves out, runs the same steps on zeros (every barrier is reached) and
+  // writes only its zeros
+  const int cidx = __builtin_amdgcn_readfirstlane(bx * (nth / CN) + cw);
+  const bool live = cidx < ncol;
+  const int cc = live ? cidx : 0;
+  const int k2 = cc / p.J1, je = cc - k2 * p.J1;
+  const size_t col = cc;
   double fac;
   int pol;
   column_policy(je, k2, p.N1, p.N2, fac, pol);
+  const bool act = live && fac != 0.0;
   cpx<R>* gc = G + col * Nt;
-  if (fac == 0.0) {
-    for (int i = lane; i < Nt; i += 64) gc[i] = cpx<R>{R(0), R(0)};
-    return;
-  }
+  if (live && !act)
+    for (int i = ct; i < Nt; i += CN) gc[i] = cpx<R>{R(0), R(0)};
   const cpx<R>* zc = Z1 + col * N3;
-  stage_in<(PPT < 16 ? PPT : 16)>(sm.a, N3, lane, 64, [&](int i) { return zc[i]; });
-  wave_sync();
+  stage_in<(PPT < 16 ? PPT : 16)>(sm.a, N3, ct, CN, [&](int i) { return act ? zc[i] : cpx<R>{R(0), R(0)}; });
+  sync_policy<WV>();
   // transpose of the unnormalised depth inverse: forward FFT
-  fft_lds_ip<false, R, true, PPT>(sm.a, p.r_N3, 1, 1, 0, sm.tw3, lane, 64);
+  fft_lds_ip<false, R, WV, PPT>(sm.a, p.r_N3, 1, 1, 0, sm.tw3, ct, CN);
   const cpx<R>* Xp = sm.a;
   const int j1 = je - p.N1 / 2;
   const double a = double(j1) * double(j1) * p.inv_L1sq + double(k2) * double(k2) * p.inv_L2sq;
@@ -502,7 +549,7 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
   // e = h3 (-x0) and h3 + 1 (+x0), and li = e - 1 above them
   const int npt = N3 + 1 + (cosm ? 1 : 0);
   const double x0 = cosm ? x_lateral<ARGS64>(p, a) : 0.0;
-  for (int e = lane; e < npt; e += 64) {
+  for (int e = ct; e < npt; e += CN) {
     int li = e, side = 0;
     if (cosm && e >= h3) {
       if (e == h3)
@@ -526,7 +573,7 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
     sm.q0[e] = lp.q0;
     sm.fr[e] = lp.fr;
   }
-  wave_sync();
+  sync_policy<WV>();
   // B'[q] = sum over l whose taps cover q of phi(x_l - q) H'(l); x_l is
   // non-decreasing in l, so the l covering q form a contiguous range.
   cpx<R>* Bp = sm.a;
@@ -537,34 +584,38 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
   const int qlo = sm.q0[0], qhi = sm.q0[npt - 1];
   // st[v] = number of points with q0 < qlo + v (v in [0, span + 1]): a count
   // per grid cell with integer LDS atomics (the counts do not depend on their
-  // order) and an inclusive prefix sum over the counts stored one cell up;
-  // the bounds of a tap window are then single reads. A span beyond the
-  // table (aliased frequencies) keeps the binary search.
+  // order) and an inclusive prefix sum over the counts stored one cell up,
+  // taken by the column's first wavefront; the bounds of a tap window are
+  // then single reads. A span beyond the table (aliased frequencies) keeps
+  // the binary search.
   const int span = qhi - qlo;
   const bool table = span <= ntt;
   int* st = sm.st;
   if (table) {
-    for (int v = lane; v <= span + 1; v += 64) st[v] = 0;
-    wave_sync();
-    for (int e = lane; e < npt; e += 64) atomicAdd(&st[sm.q0[e] - qlo + 1], 1);
-    wave_sync();
-    const int nv = span + 2, ch = (nv + 63) / 64;
-    const int v0 = lane * ch < nv ? lane * ch : nv;
-    const int v1 = v0 + ch < nv ? v0 + ch : nv;
-    int run = 0;
-    for (int v = v0; v < v1; ++v) run += st[v];
-    int incl = run;
+    for (int v = ct; v <= span + 1; v += CN) st[v] = 0;
+    sync_policy<WV>();
+    for (int e = ct; e < npt; e += CN) atomicAdd(&st[sm.q0[e] - qlo + 1], 1);
+    sync_policy<WV>();
+    if (ct < 64) {
+      const int lane = ct;
+      const int nv = span + 2, ch = (nv + 63) / 64;
+      const int v0 = lane * ch < nv ? lane * ch : nv;
+      const int v1 = v0 + ch < nv ? v0 + ch : nv;
+      int run = 0;
+      for (int v = v0; v < v1; ++v) run += st[v];
+      int incl = run;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int t = __shfl_up(incl, d, 64);
-      if (lane >= d) incl += t;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+      }
+      int acc = incl - run;
+      for (int v = v0; v < v1; ++v) {
+        acc += st[v];
+        st[v] = acc;
+      }
     }
-    int acc = incl - run;
-    for (int v = v0; v < v1; ++v) {
-      acc += st[v];
-      st[v] = acc;
-    }
-    wave_sync();
+    sync_policy<WV>();
   }
   // first point with q0 >= t
   auto lower = [&](int t, int from) {
@@ -572,7 +623,9 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
     const int v = t - qlo;
     return v <= 0 ? 0 : (v > span ? npt : st[v]);
   };
-  for (int q = lane; q < ntt; q += 64) {
+  // the transform buffer is not read here (the loop reads the per-point
+  // arrays and the table), so each B' value goes straight into it
+  for (int q = ct; q < ntt; q += CN) {
     const int qc = q < ntt / 2 ? q : q - ntt;
     cpx<R> acc = {R(0), R(0)};
     for (int m = -mwrap; m <= mwrap; ++m) {
@@ -591,35 +644,37 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
     }
     Bp[q] = acc;
   }
-  wave_sync();
-  fft_lds_ip<true, R, true, PPT>(Bp, p.r_ntt, 1, 1, 0, sm.twt, lane, 64);
+  sync_policy<WV>();
+  fft_lds_ip<true, R, WV, PPT>(Bp, p.r_ntt, 1, 1, 0, sm.twt, ct, CN);
   const cpx<R>* Ap = Bp;
-  for (int n = lane; n < Nt; n += 64) {
-    const int s = pmodc(n - Nt / 2, ntt);
-    gc[n] = Ap[s];
+  if (act) {
+    for (int n = ct; n < Nt; n += CN) {
+      const int s = pmodc(n - Nt / 2, ntt);
+      gc[n] = Ap[s];
+    }
   }
 }
 
-template <typename R, int W, bool ARGS64, int PPT, bool KBW>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW, int WPC>
 __global__ __launch_bounds__(512) void k_column_adj(KP p, int ncol, int mwrap, const cpx<R>* __restrict__ Z1,
                                                     cpx<R>* __restrict__ G) {
-  column_adj_body<R, W, ARGS64, PPT, KBW>(p, ncol, mwrap, blockIdx.x, Z1, G);
+  column_adj_body<R, W, ARGS64, PPT, KBW, WPC>(p, ncol, mwrap, blockIdx.x, Z1, G);
 }
 
 // ---------------------------------------------------------------- launchers
 
-// Columns (wavefronts) per workgroup: the count in 1..8 that keeps the most
+// Columns per workgroup (up to 512 threads): the count that keeps the most
 // wavefronts resident on a CU with 160 KB of LDS (the twiddles are shared).
 template <typename R>
-static int cols_per_wg(const KP& p, bool adj) {
+static int cols_per_wg(const KP& p, bool adj, int wpc) {
   const size_t sh = col_shared_bytes<R>(p.ntt, p.N3), per = col_wave_bytes<R>(p.ntt, p.N3, adj);
   const size_t lds = 160 * 1024;
   int best = 1;
   size_t best_waves = 0;
-  for (int c = 1; c <= 8; ++c) {
+  for (int c = 1; c * wpc <= 8; ++c) {
     const size_t wg = sh + c * per;
     if (wg > lds) break;
-    const size_t waves = c * (lds / wg);
+    const size_t waves = c * wpc * (lds / wg);
     if (waves > best_waves) {
       best_waves = waves;
       best = c;
@@ -628,33 +683,35 @@ static int cols_per_wg(const KP& p, bool adj) {
   return best;
 }
 
-// Points per lane of the per-column transforms (the larger of ntt and N3 over 64).
+// Points per thread of the per-column transforms: the larger of ntt and N3
+// over the column's threads, rounded up to a power of two (at least 4).
 static int column_ppt(const KP& p) {
   const int n = p.ntt > p.N3 ? p.ntt : p.N3;
-  const int need = (n + 63) / 64;
-  return need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
+  const int need = (n + 64 * column_wpc(p.ntt, p.N3) - 1) / (64 * column_wpc(p.ntt, p.N3));
+  return need <= 4 ? 4 : need <= 8 ? 8 : 16;
 }
 
-template <typename R, int W, bool ARGS64, int PPT, bool KBW>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW, int WPC>
 static hipError_t column_wp(const KP& p, const void* G, void* out, int spec, hipStream_t s) {
-  const int cpw = cols_per_wg<R>(p, false);
+  const int cpw = cols_per_wg<R>(p, false, WPC);
   const int ncol = p.J1 * p.K2;
   const size_t sh = col_shared_bytes<R>(p.ntt, p.N3) + cpw * col_wave_bytes<R>(p.ntt, p.N3, false);
   dim3 grid((ncol + cpw - 1) / cpw);
-  hipError_t e = allow_smem(spec ? k_column<R, W, ARGS64, true, PPT, KBW> : k_column<R, W, ARGS64, false, PPT, KBW>, sh);
+  hipError_t e = allow_smem(spec ? k_column<R, W, ARGS64, true, PPT, KBW, WPC>
+                                 : k_column<R, W, ARGS64, false, PPT, KBW, WPC>, sh);
   if (e != hipSuccess) return e;
   if (spec)
-    hipLaunchKernelGGL((k_column<R, W, ARGS64, true, PPT, KBW>), grid, dim3(64 * cpw), sh, s, p, ncol,
+    hipLaunchKernelGGL((k_column<R, W, ARGS64, true, PPT, KBW, WPC>), grid, dim3(64 * WPC * cpw), sh, s, p, ncol,
                        static_cast<const cpx<R>*>(G), out);
   else
-    hipLaunchKernelGGL((k_column<R, W, ARGS64, false, PPT, KBW>), grid, dim3(64 * cpw), sh, s, p, ncol,
-                       static_cast<const cpx<R>*>(G), out);
+    hipLaunchKernelGGL((k_column<R, W, ARGS64, false, PPT, KBW, WPC>), grid, dim3(64 * WPC * cpw), sh, s, p,
+                       ncol, static_cast<const cpx<R>*>(G), out);
   return hipGetLastError();
 }
 
-template <typename R, int W, bool ARGS64, int PPT, bool KBW>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW, int WPC>
 static hipError_t column_adj_wp(const KP& p, const void* Z1, void* G, hipStream_t s) {
-  const int cpw = cols_per_wg<R>(p, true);
+  const int cpw = cols_per_wg<R>(p, true, WPC);
   const int ncol = p.J1 * p.K2;
   const size_t sh = col_shared_bytes<R>(p.ntt, p.N3) + cpw * col_wave_bytes<R>(p.ntt, p.N3, true);
   dim3 grid((ncol + cpw - 1) / cpw);
@@ -663,33 +720,35 @@ static hipError_t column_adj_wp(const KP& p, const void* Z1, void* G, hipStream_
                                      (p.N2 / 2.0) * (p.N2 / 2.0) * p.inv_L2sq +
                                      (p.N3 / 2.0) * (p.N3 / 2.0) * p.bz);
   const int mwrap = 1 + int((xmax + W) / p.ntt);
-  hipError_t e = allow_smem(k_column_adj<R, W, ARGS64, PPT, KBW>, sh);
+  hipError_t e = allow_smem(k_column_adj<R, W, ARGS64, PPT, KBW, WPC>, sh);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_column_adj<R, W, ARGS64, PPT, KBW>), grid, dim3(64 * cpw), sh, s, p, ncol, mwrap,
-                     static_cast<const cpx<R>*>(Z1), static_cast<cpx<R>*>(G));
+  hipLaunchKernelGGL((k_column_adj<R, W, ARGS64, PPT, KBW, WPC>), grid, dim3(64 * WPC * cpw), sh, s, p, ncol,
+                     mwrap, static_cast<const cpx<R>*>(Z1), static_cast<cpx<R>*>(G));
   return hipGetLastError();
 }
 
+// (wavefronts per column, points per thread): (1, 4), (1, 8) up to 512
+// points, (4, 4), (4, 8), (4, 16) up to 4096
 template <typename R, int W, bool ARGS64, bool KBW>
 static hipError_t column_w(const KP& p, const void* G, void* out, int spec, hipStream_t s) {
-  switch (column_ppt(p)) {
-    case 4: return column_wp<R, W, ARGS64, 4, KBW>(p, G, out, spec, s);
-    case 8: return column_wp<R, W, ARGS64, 8, KBW>(p, G, out, spec, s);
-    case 16: return column_wp<R, W, ARGS64, 16, KBW>(p, G, out, spec, s);
-    case 32: return column_wp<R, W, ARGS64, 32, KBW>(p, G, out, spec, s);
-    default: return column_wp<R, W, ARGS64, 64, KBW>(p, G, out, spec, s);
-  }
+  const int ppt = column_ppt(p);
+  if (column_wpc(p.ntt, p.N3) == 1)
+    return ppt == 4 ? column_wp<R, W, ARGS64, 4, KBW, 1>(p, G, out, spec, s)
+                    : column_wp<R, W, ARGS64, 8, KBW, 1>(p, G, out, spec, s);
+  return ppt == 4 ? column_wp<R, W, ARGS64, 4, KBW, 4>(p, G, out, spec, s)
+                  : ppt == 8 ? column_wp<R, W, ARGS64, 8, KBW, 4>(p, G, out, spec, s)
+                             : column_wp<R, W, ARGS64, 16, KBW, 4>(p, G, out, spec, s);
 }
 
 template <typename R, int W, bool ARGS64, bool KBW>
 static hipError_t column_adj_w(const KP& p, const void* Z1, void* G, hipStream_t s) {
-  switch (column_ppt(p)) {
-    case 4: return column_adj_wp<R, W, ARGS64, 4, KBW>(p, Z1, G, s);
-    case 8: return column_adj_wp<R, W, ARGS64, 8, KBW>(p, Z1, G, s);
-    case 16: return column_adj_wp<R, W, ARGS64, 16, KBW>(p, Z1, G, s);
-    case 32: return column_adj_wp<R, W, ARGS64, 32, KBW>(p, Z1, G, s);
-    default: return column_adj_wp<R, W, ARGS64, 64, KBW>(p, Z1, G, s);
-  }
+  const int ppt = column_ppt(p);
+  if (column_wpc(p.ntt, p.N3) == 1)
+    return ppt == 4 ? column_adj_wp<R, W, ARGS64, 4, KBW, 1>(p, Z1, G, s)
+                    : column_adj_wp<R, W, ARGS64, 8, KBW, 1>(p, Z1, G, s);
+  return ppt == 4 ? column_adj_wp<R, W, ARGS64, 4, KBW, 4>(p, Z1, G, s)
+                  : ppt == 8 ? column_adj_wp<R, W, ARGS64, 8, KBW, 4>(p, Z1, G, s)
+                             : column_adj_wp<R, W, ARGS64, 16, KBW, 4>(p, Z1, G, s);
 }
 
 // The Kaiser-Bessel window is instantiated for the tap counts it is meant
@@ -723,43 +782,46 @@ hipError_t column_a(const KP& p, const void* in, void* out, int spec, hipStream_
 }
 
 // ---------------------------------------------------------------- batched
-template <typename R, int W, bool ARGS64, int PPT, bool KBW>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW, int WPC>
 __global__ __launch_bounds__(512) void k_column_many(const BatchProb* __restrict__ bp, WorkList wl) {
   work_loop(wl, [&](int prob, int local) {
     const BatchProb& B = bp[prob];
     const KP& p = B.kp;
-    column_body<R, W, ARGS64, false, PPT, KBW>(p, p.J1 * p.K2, local, static_cast<const cpx<R>*>(B.b0), B.b1);
+    column_body<R, W, ARGS64, false, PPT, KBW, WPC>(p, p.J1 * p.K2, local, static_cast<const cpx<R>*>(B.b0),
+                                                    B.b1);
   });
 }
 
-template <typename R, int W, bool ARGS64, int PPT, bool KBW>
+template <typename R, int W, bool ARGS64, int PPT, bool KBW, int WPC>
 static hipError_t column_many_wp(const BatchProb* bp, const WorkList& wl, int cpw, size_t smem, hipStream_t s) {
   if (wl.total <= 0) return hipSuccess;
-  auto k = k_column_many<R, W, ARGS64, PPT, KBW>;
+  auto k = k_column_many<R, W, ARGS64, PPT, KBW, WPC>;
   hipError_t e = allow_smem(k, smem);
   if (e != hipSuccess) return e;
   int per_cu = 0, dev = 0, cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64 * cpw, smem) !=
-          hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64 * WPC * cpw,
+                                                   smem) != hipSuccess || per_cu < 1)
     per_cu = 1;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const int grid = (int)std::min<long>((long)per_cu * cus, wl.total);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * cpw), smem, s, bp, wl);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPC * cpw), smem, s, bp, wl);
   return hipGetLastError();
 }
 
+// p0 carries the largest ntt and N3 of the batch: they fix the wavefronts per
+// column and the points per thread of the launch
 template <typename R, bool ARGS64>
 hipError_t column_many_a(const KP& p0, int ppt, const BatchProb* bp, const WorkList& wl, int cpw,
                                 size_t smem, hipStream_t s) {
-#define NEDNER_CMPK(WV, KB)                                                              \
-    switch (ppt) {                                                                       \
-      case 4: return column_many_wp<R, WV, ARGS64, 4, KB>(bp, wl, cpw, smem, s);         \
-      case 8: return column_many_wp<R, WV, ARGS64, 8, KB>(bp, wl, cpw, smem, s);         \
-      case 16: return column_many_wp<R, WV, ARGS64, 16, KB>(bp, wl, cpw, smem, s);       \
-      case 32: return column_many_wp<R, WV, ARGS64, 32, KB>(bp, wl, cpw, smem, s);       \
-      default: return column_many_wp<R, WV, ARGS64, 64, KB>(bp, wl, cpw, smem, s);       \
-    }
+  const int wpc = column_wpc(p0.ntt, p0.N3);
+#define NEDNER_CMPK(WV, KB)                                                                        \
+    if (wpc == 1)                                                                                  \
+      return ppt == 4 ? column_many_wp<R, WV, ARGS64, 4, KB, 1>(bp, wl, cpw, smem, s)              \
+                      : column_many_wp<R, WV, ARGS64, 8, KB, 1>(bp, wl, cpw, smem, s);             \
+    return ppt == 4 ? column_many_wp<R, WV, ARGS64, 4, KB, 4>(bp, wl, cpw, smem, s)                \
+                    : ppt == 8 ? column_many_wp<R, WV, ARGS64, 8, KB, 4>(bp, wl, cpw, smem, s)     \
+                               : column_many_wp<R, WV, ARGS64, 16, KB, 4>(bp, wl, cpw, smem, s);
 #define NEDNER_CMP(WV)                                                                   \
   case WV:                                                                               \
     if constexpr (kb_width(WV)) {                                                        \
