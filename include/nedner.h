@@ -318,6 +318,23 @@ nedner_status nedner_mip(const void* d_vol, int n1, int n2, int n3, int axis, in
 nedner_status nedner_corrcoef(const void* d_a, const void* d_b, const unsigned char* d_mask, int64_t n,
                               int dtype, double* d_result, void* d_work, size_t work_bytes, void* stream);
 
+/* nedner_corrcoef for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same kernels and the same result, bit for bit, with the partial sums
+   in a file-scope device array of 12 304 bytes (3 * 512 + 2 doubles) that
+   every device the library runs on holds until the process ends, instead of
+   a caller workspace. That size does not depend on n, so no input is too
+   large for it. The array's device address is looked up once per device, on
+   the first call made with that device current. Every call on a device
+   shares its array: calls that overlap on one device (concurrent streams or
+   threads) race and must be serialised by the caller. Allocates nothing
+   (no hipMalloc, hipFree or allocating library call); the kernels write every
+   scratch value they read, so nothing is cleared between calls. Arguments
+   and errors as nedner_corrcoef without the workspace; NEDNER_E_HIP if the
+   scratch address cannot be obtained. */
+nedner_status nedner_corrcoef_noalloc(const void* d_a, const void* d_b, const unsigned char* d_mask, int64_t n,
+                                      int dtype, double* d_result, void* stream);
+
 /* Tenenbaum sharpness of a device image (rows, cols), row-major (App. B,
    eqs. (12)-(13)): the sum of (g * U)^2 + (g^T * U)^2, g the 3x3 Sobel kernel
    [[-1, 0, 1], [-2, 0, 2], [-1, 0, 1]], over the pixels of the half-open

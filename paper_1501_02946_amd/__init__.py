@@ -81,7 +81,7 @@ EXPORTS = ["nedner_desc_init", "nedner_validate", "nedner_query", "nedner_plan_c
            "nedner_get_tuning", "nedner_set_tuning", "nedner_autotune", "nedner_execute_q",
            "nedner_execute_q_adjoint", "nedner_metrics_workspace_size", "nedner_mip",
            "nedner_corrcoef", "nedner_tenenbaum", "nedner_tenenbaum_mean",
-           "nedner_debug_inject_hip_error"]
+           "nedner_debug_inject_hip_error", "nedner_corrcoef_noalloc"]
 
 
 def _declare(L):
@@ -105,6 +105,7 @@ def _declare(L):
     L.nedner_metrics_workspace_size.restype = sz
     L.nedner_mip.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
     L.nedner_corrcoef.argtypes = [vp, vp, vp, i64, i32, vp, vp, sz, vp]
+    L.nedner_corrcoef_noalloc.argtypes = [vp, vp, vp, i64, i32, vp, vp]
     L.nedner_tenenbaum.argtypes = [vp, i64, i64, i64, i64, i64, i64, i32, vp, vp, sz, vp]
     L.nedner_tenenbaum_mean.argtypes = [vp, i64, i64, i64, i64, i64, i64, i32, vp, vp, sz, vp]
     L.nedner_execute_q_adjoint.argtypes = [vp, vp, vp, vp]

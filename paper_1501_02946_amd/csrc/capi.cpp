@@ -1697,6 +1697,21 @@ nedner_status nedner_corrcoef(const void* d_a, const void* d_b, const unsigned c
 }
 
 
+nedner_status nedner_corrcoef_noalloc(const void* d_a, const void* d_b, const unsigned char* d_mask, int64_t n,
+                                      int dtype, double* d_result, void* stream) {
+  if (!d_a || !d_b || !d_result) return fail(NEDNER_E_ARG, "NULL device pointer");
+  if (n < 1) return fail(NEDNER_E_ARG, "n must be positive");
+  if (dtype != NEDNER_DTYPE_F32 && dtype != NEDNER_DTYPE_F64) return fail(NEDNER_E_ARG, "unknown dtype");
+  // the scratch holds a fixed number of partial sums whatever n: there is no
+  // input size it cannot serve
+  if (nedner::noalloc_scratch_bytes() > nedner::METRICS_WORK_BYTES)
+    return fail(NEDNER_E_WORKSPACE, "scratch larger than its stated maximum");
+  const hipError_t e = nedner::launch_corrcoef_noalloc(d_a, d_b, d_mask, long(n), dtype == NEDNER_DTYPE_F64,
+                                                       d_result, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NEDNER_OK
+                         : fail(NEDNER_E_HIP, std::string("corrcoef_noalloc: ") + hipGetErrorString(e));
+}
+
 nedner_status nedner_tenenbaum(const void* d_img, int64_t rows, int64_t cols, int64_t r0, int64_t r1,
                                int64_t c0, int64_t c1, int dtype, double* d_result, void* d_work,
                                size_t work_bytes, void* stream) {

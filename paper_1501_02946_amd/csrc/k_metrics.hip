@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "kparams.hpp"
 
@@ -214,6 +215,55 @@ hipError_t launch_corrcoef(const void* a, const void* b, const unsigned char* ma
                            double* result, void* work, hipStream_t s) {
   return dbl ? corrcoef_t<double>(a, b, mask, n, result, work, s)
              : corrcoef_t<float>(a, b, mask, n, result, work, s);
+}
+
+// ---------------------------------------------------------------- no allocation
+
+// Scratch of the allocation-free correlation coefficient: the partial sums of
+// the two passes and the means, in a file-scope device array instead of a
+// caller workspace. Every device holds its own copy at its own address; host
+// code reaches it only through the address hipGetSymbolAddress returns, taken
+// once per device with that device current (the array's name in host code is
+// a host-side stand-in, not a device address). Calls that overlap on one
+// device share it and race.
+constexpr int NOALLOC_SCRATCH_DOUBLES = 3 * MET_BLOCKS + 2;
+static_assert(sizeof(double) * NOALLOC_SCRATCH_DOUBLES <= METRICS_WORK_BYTES, "no-allocation scratch");
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return sizeof(double) * NOALLOC_SCRATCH_DOUBLES; }
+
+// The current device's scratch address, looked up on the first call on that
+// device (the device is current during the lookup).
+hipError_t noalloc_scratch(void** ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_corrcoef_noalloc(const void* a, const void* b, const unsigned char* mask, long n, bool dbl,
+                                   double* result, hipStream_t s) {
+  void* work = nullptr;
+  const hipError_t e = noalloc_scratch(&work);
+  if (e != hipSuccess) return e;
+  // the kernels write every partial sum they read: nothing needs clearing
+  return launch_corrcoef(a, b, mask, n, dbl, result, work, s);
 }
 
 hipError_t launch_tenenbaum(const void* img, long rows, long cols, long r0, long r1, long c0, long c1, bool dbl,

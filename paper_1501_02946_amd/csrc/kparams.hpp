@@ -127,6 +127,11 @@ hipError_t launch_corrcoef(const void* a, const void* b, const unsigned char* ma
                            double* result, void* work, hipStream_t s);
 hipError_t launch_tenenbaum(const void* img, long rows, long cols, long r0, long r1, long c0, long c1, bool dbl,
                             double scale, double* result, void* work, hipStream_t s);
+// The correlation coefficient with its partial sums in a file-scope device
+// array (k_metrics.hip) instead of a caller workspace: allocates nothing.
+hipError_t launch_corrcoef_noalloc(const void* a, const void* b, const unsigned char* mask, long n, bool dbl,
+                                   double* result, hipStream_t s);
+size_t noalloc_scratch_bytes();
 hipError_t launch_gather(const KP& p, const void* U, void* g, hipStream_t s);
 hipError_t launch_lat_a(const KP& p, const void* U, void* V, hipStream_t s);
 hipError_t launch_lat_b(const KP& p, const void* V, void* G, hipStream_t s);

@@ -24,6 +24,11 @@ hipError_t launch_tenenbaum(const void*, long, long, long, long, long, long, boo
                             hipStream_t) {
   return unavailable();
 }
+hipError_t launch_corrcoef_noalloc(const void*, const void*, const unsigned char*, long, bool, double*,
+                                   hipStream_t) {
+  return unavailable();
+}
+size_t noalloc_scratch_bytes() { return 0; }
 hipError_t launch_gather(const KP&, const void*, void*, hipStream_t) { return unavailable(); }
 hipError_t launch_lat_a(const KP&, const void*, void*, hipStream_t) { return unavailable(); }
 hipError_t launch_lat_b(const KP&, const void*, void*, hipStream_t) { return unavailable(); }
