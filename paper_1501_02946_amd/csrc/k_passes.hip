@@ -51,6 +51,24 @@ __device__ __forceinline__ cpx<R>* pass_fft(Smem<R>& sm, const Radices& rd, int 
   }
 }
 
+// XCD-aware tile order: the hardware deals workgroups round-robin to the 8
+// XCDs, so workgroup b goes to XCD b & 7. Tile L = (b & 7) per + (b >> 3)
+// gives each XCD a contiguous run of tiles in (bx fastest, by) order, so that
+// the neighbouring tiles along the contiguous axis, which share cache lines
+// at their edges, run under the same L2. Returns false past the last tile.
+// The first-axis passes (lat_b, adj_b), whose lines are K2 Nt points apart,
+// measured faster in plain launch order (REMAP false): there the tile is
+// blockIdx.x itself.
+template <bool REMAP = true>
+__device__ __forceinline__ bool xcd_tile(int gx, int ntile, int& bx, int& by) {
+  const int per = (ntile + 7) >> 3;
+  const int L = REMAP ? (blockIdx.x & 7) * per + (blockIdx.x >> 3) : int(blockIdx.x);
+  if (L >= ntile) return false;
+  by = L / gx;
+  bx = L - by * gx;
+  return true;
+}
+
 // ---------------------------------------------------------------- forward
 
 template <typename R, bool IP>
@@ -85,9 +103,11 @@ __device__ __forceinline__ void lat_a_body(const KP& p, int TB, int bx, int by, 
 }
 
 template <typename R, bool IP>
-__global__ __launch_bounds__(512) void k_lat_a(KP p, int TB, const R* __restrict__ U,
+__global__ __launch_bounds__(512) void k_lat_a(KP p, int TB, int gx, int ntile, const R* __restrict__ U,
                                                cpx<R>* __restrict__ V) {
-  lat_a_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, U, V);
+  int bx, by;
+  if (!xcd_tile(gx, ntile, bx, by)) return;
+  lat_a_body<R, IP>(p, TB, bx, by, U, V);
 }
 
 template <typename R, bool IP>
@@ -120,9 +140,11 @@ __device__ __forceinline__ void lat_b_body(const KP& p, int TB, int bx, int by, 
 }
 
 template <typename R, bool IP>
-__global__ __launch_bounds__(512) void k_lat_b(KP p, int TB, const cpx<R>* __restrict__ V,
+__global__ __launch_bounds__(512) void k_lat_b(KP p, int TB, int gx, int ntile, const cpx<R>* __restrict__ V,
                                                cpx<R>* __restrict__ G) {
-  lat_b_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, V, G);
+  int bx, by;
+  if (!xcd_tile<false>(gx, ntile, bx, by)) return;
+  lat_b_body<R, IP>(p, TB, bx, by, V, G);
 }
 
 template <typename R, bool IP>
@@ -155,9 +177,11 @@ __device__ __forceinline__ void pass_c_body(const KP& p, int TB, int bx, int by,
 }
 
 template <typename R, bool IP>
-__global__ __launch_bounds__(512) void k_pass_c(KP p, int TB, const cpx<R>* __restrict__ Z1,
+__global__ __launch_bounds__(512) void k_pass_c(KP p, int TB, int gx, int ntile, const cpx<R>* __restrict__ Z1,
                                                 cpx<R>* __restrict__ Z2) {
-  pass_c_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, Z1, Z2);
+  int bx, by;
+  if (!xcd_tile(gx, ntile, bx, by)) return;
+  pass_c_body<R, IP>(p, TB, bx, by, Z1, Z2);
 }
 
 template <typename R, bool IP>
@@ -195,9 +219,11 @@ __device__ __forceinline__ void pass_d_body(const KP& p, int TB, int bx, int by,
 }
 
 template <typename R, bool IP>
-__global__ __launch_bounds__(512) void k_pass_d(KP p, int TB, const cpx<R>* __restrict__ Z2,
+__global__ __launch_bounds__(512) void k_pass_d(KP p, int TB, int gx, int ntile, const cpx<R>* __restrict__ Z2,
                                                 R* __restrict__ vol) {
-  pass_d_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, Z2, vol);
+  int bx, by;
+  if (!xcd_tile(gx, ntile, bx, by)) return;
+  pass_d_body<R, IP>(p, TB, bx, by, Z2, vol);
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -235,9 +261,11 @@ __device__ __forceinline__ void adj_d_body(const KP& p, int TB, int bx, int by, 
 }
 
 template <typename R, bool IP>
-__global__ __launch_bounds__(512) void k_adj_d(KP p, int TB, const R* __restrict__ vol,
+__global__ __launch_bounds__(512) void k_adj_d(KP p, int TB, int gx, int ntile, const R* __restrict__ vol,
                                                cpx<R>* __restrict__ Z2) {
-  adj_d_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, vol, Z2);
+  int bx, by;
+  if (!xcd_tile(gx, ntile, bx, by)) return;
+  adj_d_body<R, IP>(p, TB, bx, by, vol, Z2);
 }
 
 template <typename R, bool IP>
@@ -269,9 +297,11 @@ __device__ __forceinline__ void adj_c_body(const KP& p, int TB, int bx, int by, 
 }
 
 template <typename R, bool IP>
-__global__ __launch_bounds__(512) void k_adj_c(KP p, int TB, const cpx<R>* __restrict__ Z2,
+__global__ __launch_bounds__(512) void k_adj_c(KP p, int TB, int gx, int ntile, const cpx<R>* __restrict__ Z2,
                                                cpx<R>* __restrict__ Z1) {
-  adj_c_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, Z2, Z1);
+  int bx, by;
+  if (!xcd_tile(gx, ntile, bx, by)) return;
+  adj_c_body<R, IP>(p, TB, bx, by, Z2, Z1);
 }
 
 template <typename R, bool IP>
@@ -308,9 +338,11 @@ __device__ __forceinline__ void adj_b_body(const KP& p, int TB, int bx, int by, 
 }
 
 template <typename R, bool IP>
-__global__ __launch_bounds__(512) void k_adj_b(KP p, int TB, const cpx<R>* __restrict__ G,
+__global__ __launch_bounds__(512) void k_adj_b(KP p, int TB, int gx, int ntile, const cpx<R>* __restrict__ G,
                                                cpx<R>* __restrict__ V) {
-  adj_b_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, G, V);
+  int bx, by;
+  if (!xcd_tile<false>(gx, ntile, bx, by)) return;
+  adj_b_body<R, IP>(p, TB, bx, by, G, V);
 }
 
 template <typename R, bool IP>
@@ -353,9 +385,11 @@ __device__ __forceinline__ void adj_a_body(const KP& p, int TB, int bx, int by, 
 }
 
 template <typename R, bool IP>
-__global__ __launch_bounds__(512) void k_adj_a(KP p, int TB, const cpx<R>* __restrict__ V,
+__global__ __launch_bounds__(512) void k_adj_a(KP p, int TB, int gx, int ntile, const cpx<R>* __restrict__ V,
                                                R* __restrict__ U) {
-  adj_a_body<R, IP>(p, TB, blockIdx.x, blockIdx.y, V, U);
+  int bx, by;
+  if (!xcd_tile(gx, ntile, bx, by)) return;
+  adj_a_body<R, IP>(p, TB, bx, by, V, U);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -382,14 +416,15 @@ static size_t smem_for(int n, int TB, bool ip) {
     const bool ip = p.pass_ip != 0;                                                             \
     const int nth = pass_threads_for(p, n, TB);                                                 \
     const size_t sh = smem_for<R>(n, TB, ip);                                                   \
-    dim3 grid(((GYLINES) + TB - 1) / TB, (GX));                                                 \
+    const int gx = ((GYLINES) + TB - 1) / TB, ntile = gx * (GX);                                \
+    dim3 grid(8 * ((ntile + 7) / 8));                                                           \
     hipError_t e = ip ? allow_smem(KERNEL<R, true>, sh) : allow_smem(KERNEL<R, false>, sh);     \
     if (e != hipSuccess) return e;                                                              \
     if (ip)                                                                                     \
-      hipLaunchKernelGGL((KERNEL<R, true>), grid, dim3(nth), sh, s, p, TB,                      \
+      hipLaunchKernelGGL((KERNEL<R, true>), grid, dim3(nth), sh, s, p, TB, gx, ntile,           \
                          static_cast<const IN_T*>(in), static_cast<OUT_T*>(out));               \
     else                                                                                        \
-      hipLaunchKernelGGL((KERNEL<R, false>), grid, dim3(nth), sh, s, p, TB,                     \
+      hipLaunchKernelGGL((KERNEL<R, false>), grid, dim3(nth), sh, s, p, TB, gx, ntile,          \
                          static_cast<const IN_T*>(in), static_cast<OUT_T*>(out));               \
     return hipGetLastError();                                                                   \
   }
