@@ -78,11 +78,11 @@ typedef enum {
   NEDNER_FP64 = 0,              /* every step in double */
   NEDNER_FP32 = 1,              /* float data, sums and transforms; double arguments */
   NEDNER_FP32_COMPENSATED = 2,  /* as FP32, with compensated float sums where many terms meet:
-                                   the spreading sums each grid value as two float partial
-                                   sums (the sensors of the first and of the second half of
-                                   its sweep window) joined by an error-free TwoSum, the
-                                   result rounded once; the adjoint gather adds its W row
-                                   sums with Kahan compensation */
+                                   the spreading holds each grid value as a pair hi + lo of
+                                   floats, adds terms to lo and folds lo into hi with Kahan's
+                                   update after every 8 terms (blocked compensated summation),
+                                   rounding hi + lo once; the adjoint gather adds its W row
+                                   sums with Kahan's update */
   NEDNER_FP32_PLAIN = 3,        /* float everywhere, arguments included */
   NEDNER_FP32_WIDE = 4          /* float data; spreading sums, the adjoint gather's row-sum
                                    merges and the first-axis spreading weights in double */

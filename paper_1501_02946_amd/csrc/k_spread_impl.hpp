@@ -91,12 +91,19 @@ __device__ __forceinline__ int pmod(int a, int n) {
 // thus waits on global memory once per batch, for loads issued a whole batch
 // earlier. Each lane reads back only what it wrote, so no barrier is needed.
 //
-// Accumulation: in A (float or double registers), or, with KAHAN, in float
-// with Kahan's compensation per term (each grid value keeps a running sum and
-// the negated low part the sum has lost; a term enters as
-// y = w gt - c (one rounding), s' = s + y, c = (s' - s) - y), and the
-// compensated sum s - c is rounded to the data type once, when the row
-// retires.
+// Accumulation: in A (float or double registers), or, with KAHAN, as blocked
+// compensated float sums (FABsum: Blanchard, Higham and Mary, SIAM J. Sci.
+// Comput. 42 (2020)): every grid value of the ring is an unevaluated pair
+// hi + lo of floats. Terms enter lo with one fused multiply-add each, exactly
+// as in the plain path; after every FOLD entries of the sweep, lo of every
+// value (the terms since the last fold plus the previous compensation) is
+// added to hi with Kahan's update t = hi + lo, lo' = lo - (t - hi), hi = t,
+// which keeps in lo the part the addition lost. A grid value thus sees the
+// rounding of a plain float sum only over blocks of at most FOLD terms, and
+// the blocks are summed with compensation; hi + lo is rounded to the data
+// type once, when the row retires. A fold costs 3 operations per value, so
+// the compensation adds 3/FOLD operations per term, against three per term
+// for Kahan's update on every term.
 // Table pointers are separate __restrict__ parameters so that the compiler
 // knows they are read-only for the whole kernel and fetches the wave-uniform
 // ones (list entries, first-axis weights) through the scalar cache.
@@ -140,9 +147,12 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
   const unsigned toff = lane_ok ? unsigned(tb) : 0u;
 
   static_assert(!KAHAN || sizeof(A) == 4, "the compensated sums are float");
+  // acc: the sums (plain), or the low parts lo (KAHAN); hi: the high parts
   constexpr int KW = KAHAN ? W : 1, KT = KAHAN ? TT : 1;
+  constexpr int FOLD = 8;
+  int since_fold = 0;
   A acc[W][TT];
-  A cmp[KW][KT];
+  A hi[KW][KT];
 #pragma unroll
   for (int k = 0; k < W; ++k)
 #pragma unroll
@@ -150,7 +160,7 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
 #pragma unroll
   for (int k = 0; k < KW; ++k)
 #pragma unroll
-    for (int t = 0; t < KT; ++t) cmp[k][t] = A(0);
+    for (int t = 0; t < KT; ++t) hi[k][t] = A(0);
 
   int e = cb[0];
   const int eall = cb[Vend - Vstart + 1];
@@ -226,30 +236,36 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
 #pragma unroll
           for (int k = 0; k < W; ++k) {
             const int sl = (r + k + W / 2 + 1) % W;
-            if constexpr (KAHAN) {
-              const A y = fmaf(A(wc[k]), gt, -cmp[sl % KW][t % KT]);
-              const A s2 = acc[sl][t] + y;
-              cmp[sl % KW][t % KT] = (s2 - acc[sl][t]) - y;
-              acc[sl][t] = s2;
-            } else {
-              acc[sl][t] += A(wc[k]) * gt;
-            }
+            acc[sl][t] += A(wc[k]) * gt;
           }
         }
         ++e;
+        if constexpr (KAHAN) {
+          if (++since_fold == FOLD) {
+            since_fold = 0;
+#pragma unroll
+            for (int sl = 0; sl < W; ++sl)
+#pragma unroll
+              for (int t = 0; t < TT; ++t) {
+                const A tsum = hi[sl][t] + acc[sl][t];
+                acc[sl][t] = acc[sl][t] - (tsum - hi[sl][t]);
+                hi[sl][t] = tsum;
+              }
+          }
+        }
       }
       const int slot = (r + W / 2 + 1) % W;
       const int Q = V - W / 2 + 1;
       if (Q >= S0 && Q < S1 && lane_ok) {
         R o[TT];
 #pragma unroll
-        for (int t = 0; t < TT; ++t) o[t] = KAHAN ? R(acc[slot][t] - cmp[slot % KW][t % KT]) : R(acc[slot][t]);
+        for (int t = 0; t < TT; ++t) o[t] = KAHAN ? R(hi[slot % KW][t % KT] + acc[slot][t]) : R(acc[slot][t]);
         store_tt<TT>(U + ((size_t)Q * p.n2 + q2) * Nt + tb, o, TT, VEC);
       }
 #pragma unroll
       for (int t = 0; t < TT; ++t) {
         acc[slot][t] = A(0);
-        if constexpr (KAHAN) cmp[slot % KW][t % KT] = A(0);
+        if constexpr (KAHAN) hi[slot % KW][t % KT] = A(0);
       }
     }
   }
