@@ -132,6 +132,11 @@ def spread_peak(prec):
     return FP64_VECTOR_TFLOPS if prec in ("fp64", "fp32w") else FP32_VECTOR_TFLOPS
 
 
+# FP32 multiply-adds issued one per lane (the kernels are built without packed
+# FP32 instructions): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
 # kernel name prefix -> stage, and the source file that defines the kernel
 STAGE_KERNELS = {
     "k_spread": ("spread", "k_spread_impl.hpp"), "k_lat_a": ("lat_a", "k_passes.hip"),
@@ -150,59 +155,74 @@ def kernel_source_hash(stage):
     return h.hexdigest()[:16]
 
 
+# the launch-shape fields each stage's kernel depends on
+STAGE_SHAPE = {
+    "spread": ("rows_per_wave", "time_per_lane", "spread_depth"),
+    "lat_a": ("pass_lines", "pass_threads", "pass_inplace"),
+    "lat_b": ("pass_lines", "pass_threads", "pass_inplace"),
+    "pass_c": ("pass_lines", "pass_threads", "pass_inplace"),
+    "pass_d": ("pass_lines", "pass_threads", "pass_inplace"),
+    "column": (),
+}
+
+
+def traffic_key(workload, prec, stage, tuning):
+    shape = ",".join(f"{k}={tuning[k]}" for k in STAGE_SHAPE[stage])
+    return f"{workload}:{prec}:{stage}" + (f":{shape}" if shape else "")
+
+
 def measured_traffic(workload, prec, stage, tuning):
     """HBM bytes per launch from committed rocprofv3 counters, if still current:
-    same kernel source and same launch shape, else None."""
+    same kernel source and same launch shape of that kernel, else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or stage not in STAGE_SHAPE:
         return None
     with open(path) as fh:
         d = json.load(fh)
-    rec = d.get(f"{workload}:{prec}:{stage}")
+    rec = d.get(traffic_key(workload, prec, stage, tuning))
     if not rec or rec.get("source_hash") != kernel_source_hash(stage):
-        return None
-    if rec.get("tuning") != {k: tuning[k] for k in rec.get("tuning", {})}:
         return None
     return rec.get("bytes")
 
 
-def _counter_means(path):
-    """Mean counter value per kernel (KiB per dispatch) of a rocprofv3 counter CSV."""
-    import csv
-    acc = {}
-    with open(path, newline="") as fh:
-        for r in csv.DictReader(fh):
-            name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").strip()
-            name = name.split("::")[-1]
-            acc.setdefault(name, []).append(float(r["Counter_Value"]))
-    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+def summarize_counters(root, workload, prec):
+    """HBM traffic per stage from rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE) of this script, each scaled by what the same counter reads for
+    a plain device copy of known size (the --copy-calibration run).
 
-
-def summarize_counters(root, workload, prec, tuning):
-    """HBM traffic per stage from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)
-    of this script, each scaled by what the same counter reads for a plain
-    device copy of known size (the --copy-calibration run)."""
-    out = {}
+    Layout under root: copy_calibration.json and copy_<COUNTER>/ (the copy
+    runs), and one folder per counted launch shape holding bench_line.json
+    (the JSON line the FETCH_SIZE run printed, with its launch shape) and
+    <COUNTER>/<workload>_counter_collection.csv."""
+    from paper_1501_02946_amd.profiling import counter_means
+    with open(os.path.join(root, "copy_calibration.json")) as fh:
+        nbytes = json.load(fh)["copy_bytes"]
     scale = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
-        cal = _counter_means(os.path.join(root, f"pmc_{c}", "copy_counter_collection.csv"))
-        kib, _ = cal["__amd_rocclr_copyBuffer"]
+        cal = counter_means(os.path.join(root, f"copy_{c}", "copy_counter_collection.csv"))
+        kib, _ = cal["__amd_rocclr_copyBuffer"][c]
         # the copy reads and writes copy_bytes each
-        with open(os.path.join(root, "copy_calibration.json")) as fh:
-            nbytes = json.load(fh)["copy_bytes"]
         scale[c] = nbytes / (kib * 1024.0)
-    fetch = _counter_means(os.path.join(root, "pmc_FETCH_SIZE", f"{workload}_counter_collection.csv"))
-    write = _counter_means(os.path.join(root, "pmc_WRITE_SIZE", f"{workload}_counter_collection.csv"))
-    for kname, (stage, _) in STAGE_KERNELS.items():
-        if kname not in fetch or kname not in write:
+    out = {}
+    for sub in sorted(os.listdir(root)):
+        line = os.path.join(root, sub, "bench_line.json")
+        if not os.path.exists(line):
             continue
-        fk, n = fetch[kname]
-        wk, _ = write[kname]
-        b = fk * 1024 * scale["FETCH_SIZE"] + wk * 1024 * scale["WRITE_SIZE"]
-        out[f"{workload}:{prec}:{stage}"] = dict(
-            bytes=int(round(b)), fetch_kib=round(fk, 1), write_kib=round(wk, 1),
-            fetch_scale=round(scale["FETCH_SIZE"], 4), write_scale=round(scale["WRITE_SIZE"], 4),
-            dispatches=n, source_hash=kernel_source_hash(stage), tuning=tuning)
+        with open(line) as fh:
+            tuning = json.loads(fh.read().strip().splitlines()[-1])["tuning"]
+        fetch = counter_means(os.path.join(root, sub, "FETCH_SIZE", f"{workload}_counter_collection.csv"))
+        write = counter_means(os.path.join(root, sub, "WRITE_SIZE", f"{workload}_counter_collection.csv"))
+        for kname, (stage, _) in STAGE_KERNELS.items():
+            if kname not in fetch or kname not in write:
+                continue
+            fk, n = fetch[kname]["FETCH_SIZE"]
+            wk, _ = write[kname]["WRITE_SIZE"]
+            b = fk * 1024 * scale["FETCH_SIZE"] + wk * 1024 * scale["WRITE_SIZE"]
+            out[traffic_key(workload, prec, stage, tuning)] = dict(
+                bytes=int(round(b)), fetch_kib=round(fk, 1), write_kib=round(wk, 1),
+                fetch_scale=round(scale["FETCH_SIZE"], 4), write_scale=round(scale["WRITE_SIZE"], 4),
+                dispatches=n, source_hash=kernel_source_hash(stage),
+                shape={k: tuning[k] for k in STAGE_SHAPE[stage]})
     return out
 
 
@@ -247,6 +267,11 @@ def roofline_of(stages, model, prec, equi=False):
         ach = model[dom]["flops"] / tdom / 1e12
         roof = dict(bound="alu", achieved=round(ach, 3), peak=peak, unit="TFLOP/s",
                     frac=round(ach / peak, 4))
+        if peak == FP32_VECTOR_TFLOPS:
+            # the published peak counts packed FP32 issue, which this build
+            # does not use; the rate its unpacked multiply-adds can reach
+            roof["peak_unpacked_fp32"] = round(FP32_UNPACKED_TFLOPS, 1)
+            roof["frac_unpacked_fp32"] = round(ach / FP32_UNPACKED_TFLOPS, 4)
     else:
         ach = model[dom]["bytes"] / tdom / 1e9
         roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -391,7 +416,7 @@ def leg_batch(torch, N, a, probs, pool):
     import numpy as np
     kws = [dict(xy=p.xy, h=p.h, nt=p.nt, dt=p.dt, volume=(p.n1, p.n2, p.n3)) for p in probs]
     bp = N.BatchPlan(kws, precision=a.precision)
-    tune = bp.autotune()
+    tune = None if a.no_autotune else bp.autotune()
     dt = torch.float64 if a.precision == "fp64" else torch.float32
     gs = [torch.as_tensor(p.g, dtype=dt, device=bp.device) for p in probs]
     outs = [torch.empty((p.n1, p.n2, p.n3), dtype=dt, device=bp.device) for p in probs]
@@ -458,36 +483,37 @@ def leg_batch(torch, N, a, probs, pool):
 
 def write_traffic(a):
     """Merge the measured per-stage HBM bytes into profiles/traffic.json and print
-    them next to the algorithmic bytes, with the launch shape of the counted run."""
+    them next to the algorithmic bytes, with the launch shape of each counted run."""
     import paper_1501_02946_amd as N
     import synth
     import torch  # noqa: F401  (the binding loads torch first)
     p = synth.config(a.workload)
     info = N.query(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), h=p.h, c=p.c, t0=p.t0,
                    precision=a.precision)
-    # the JSON line the FETCH_SIZE-counted bench run printed: its launch shape
-    with open(os.path.join(a.summarize_counters, "bench_line.json")) as fh:
-        tuning = json.loads(fh.read().strip().splitlines()[-1])["tuning"]
-    rec = summarize_counters(a.summarize_counters, a.workload, a.precision, tuning)
+    rec = summarize_counters(a.summarize_counters, a.workload, a.precision)
     path = os.path.join(ROOT, "profiles", "traffic.json")
     d = {}
     if os.path.exists(path):
         with open(path) as fh:
             d = json.load(fh)
+    # entries of the same workload and precision are replaced as a whole
+    d = {k: v for k, v in d.items() if not k.startswith(f"{a.workload}:{a.precision}:")}
     d.update(rec)
     with open(path, "w") as fh:
         json.dump(d, fh, indent=1, sort_keys=True)
         fh.write("\n")
     model = stage_model(p, info, a.precision)
-    print("| stage | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | algorithmic bytes | ratio |")
-    print("|---|---|---|---|---|---|")
-    for k, r in rec.items():
-        st = k.split(":")[-1]
+    print("| stage | launch shape | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | "
+          "algorithmic bytes | ratio |")
+    print("|---|---|---|---|---|---|---|")
+    for k, r in sorted(rec.items()):
+        st = k.split(":")[2]
         alg = model[st]["bytes"]
-        print(f"| {st} | {r['fetch_kib']} | {r['write_kib']} | {r['bytes']} | {alg} | "
+        shape = " ".join(f"{x}={y}" for x, y in r["shape"].items()) or "-"
+        print(f"| {st} | {shape} | {r['fetch_kib']} | {r['write_kib']} | {r['bytes']} | {alg} | "
               f"{r['bytes'] / alg:.3f} |")
-    print(f"scale factors: FETCH_SIZE x{next(iter(rec.values()))['fetch_scale']}, "
-          f"WRITE_SIZE x{next(iter(rec.values()))['write_scale']}")
+    r0 = next(iter(rec.values()))
+    print(f"scale factors: FETCH_SIZE x{r0['fetch_scale']}, WRITE_SIZE x{r0['write_scale']}")
     return 0
 
 
@@ -497,9 +523,11 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32c", "fp32w", "fp32", "fp32_plain", "fp64"])
+    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32w", "fp32", "fp32_plain", "fp64"])
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plan's default launch shape instead of the autotuner's")
+    ap.add_argument("--shape", default="", metavar="K=V,...",
+                    help="launch-shape fields to set instead of autotuning (e.g. rows_per_wave=64)")
     ap.add_argument("--quick", action="store_true",
                     help="headline and stage times only (no other legs, no oracle)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip every oracle run")
@@ -565,7 +593,15 @@ def main(argv=None):
     plan = make_plan(N, p, a.precision, flags=flags)
     g = torch.as_tensor(p.g, dtype=plan.dtype, device=plan.device).contiguous()
     out = torch.empty((p.n1, p.n2, p.n3), dtype=plan.dtype, device=plan.device)
-    if not a.no_autotune and not equi:
+    if a.shape:
+        t = dict(plan.tuning)
+        for kv in a.shape.split(","):
+            k, v = kv.split("=")
+            if k not in t:
+                raise SystemExit(f"unknown launch-shape field {k!r}")
+            t[k] = int(v)
+        plan.set_tuning(t)
+    elif not a.no_autotune and not equi:
         # launch shape by timing candidates (sweep length, samples per lane,
         # FFT-pass shape) before the timed region; the legs below reuse it
         import tempfile
