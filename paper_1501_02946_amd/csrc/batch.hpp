@@ -59,6 +59,7 @@ hipError_t launch_column_many(const KP& p0, const BatchProb* bp, const WorkList&
                               size_t smem, hipStream_t s);
 size_t column_wave_bytes_host(const KP& p);
 int column_wpc_host(const KP& p);
+int column_ppt_host(const KP& p);
 size_t column_shared_bytes_host(const KP& p);
 
 }  // namespace nedner

@@ -582,12 +582,23 @@ struct nedner_plan_s {
   // batched plan state (subs non-empty)
   nedner::BatchProb* d_bp = nullptr;       // device problem table
   int2* d_items = nullptr;                 // work lists of all stages, concatenated
-  int* d_counters = nullptr;               // one queue head per stage
+  int* d_counters = nullptr;               // queue heads: one per stage, then one per column class
   int stage_off[nedner::ST_COUNT] = {};    // offset of each stage's list in d_items
   int stage_total[nedner::ST_COUNT] = {};
   size_t pass_smem[nedner::ST_COUNT] = {};
-  size_t col_smem = 0;
-  int col_cpw = 1;
+  // The NER column kernel's shape (wavefronts per column, points per thread)
+  // is a compile-time one, set by the transform length: the problems of a
+  // batch fall into classes of equal shape, each with its own persistent
+  // launch, work list (inside the column stage's list) and queue head.
+  struct ColClass {
+    KP kp0{};          // largest transform of the class (fixes the launch's shape)
+    int cpw = 1;       // columns per workgroup
+    size_t smem = 0;   // LDS per workgroup
+    int off = 0, total = 0;
+    std::vector<int> members;
+  };
+  std::vector<ColClass> col_classes;
+  int ncounters = nedner::ST_COUNT;
   KP kp0{};                                // uniform launch parameters of the batch
   std::vector<size_t> sub_off;             // workspace slice of each problem
   void* d_items_alloc = nullptr;           // current work-list allocation (also in d_items)
@@ -1003,30 +1014,52 @@ nedner_status create_batch(const nedner_desc* descs, int count, int device, nedn
     }
     bp->subs.push_back(sp);
   }
-  // uniform launch parameters; the largest per-column transform sets the register bound
+  // uniform launch parameters of the other stages; the column stage by class
   bp->kp0 = bp->subs[0]->kp;
-  size_t wave_max = 0, shared_max = 0;
   for (auto* sp : bp->subs) {
     bp->kp0.ntt = std::max(bp->kp0.ntt, sp->kp.ntt);
     bp->kp0.N3 = std::max(bp->kp0.N3, sp->kp.N3);
-    wave_max = std::max(wave_max, nedner::column_wave_bytes_host(sp->kp));
-    shared_max = std::max(shared_max, nedner::column_shared_bytes_host(sp->kp));
   }
-  // columns per workgroup (of wpc wavefronts each, at most 512 threads)
-  const int wpc = nedner::column_wpc_host(bp->kp0);
-  int best = 1;
-  size_t best_waves = 0;
-  for (int cw = 1; cw * wpc <= 8; ++cw) {
-    const size_t wg = shared_max + cw * wave_max;
-    if (wg > 160 * 1024) break;
-    const size_t waves = cw * wpc * ((160 * 1024) / wg);
-    if (waves > best_waves) {
-      best_waves = waves;
-      best = cw;
+  for (int i = 0; i < count; ++i) {
+    const KP& k = bp->subs[i]->kp;
+    const int wpc = nedner::column_wpc_host(k), ppt = nedner::column_ppt_host(k);
+    size_t ci = 0;
+    while (ci < bp->col_classes.size() && !(nedner::column_wpc_host(bp->col_classes[ci].kp0) == wpc &&
+                                            nedner::column_ppt_host(bp->col_classes[ci].kp0) == ppt))
+      ++ci;
+    if (ci == bp->col_classes.size()) {
+      bp->col_classes.emplace_back();
+      bp->col_classes.back().kp0 = k;
     }
+    auto& c = bp->col_classes[ci];
+    c.kp0.ntt = std::max(c.kp0.ntt, k.ntt);
+    c.kp0.N3 = std::max(c.kp0.N3, k.N3);
+    c.members.push_back(i);
   }
-  bp->col_cpw = best;
-  bp->col_smem = shared_max + best * wave_max;
+  for (auto& c : bp->col_classes) {
+    size_t wave_max = 0, shared_max = 0;
+    for (int i : c.members) {
+      wave_max = std::max(wave_max, nedner::column_wave_bytes_host(bp->subs[i]->kp));
+      shared_max = std::max(shared_max, nedner::column_shared_bytes_host(bp->subs[i]->kp));
+    }
+    // columns per workgroup (of wpc wavefronts each, at most 512 threads):
+    // the most resident wavefronts per CU within its 160 KB of LDS
+    const int wpc = nedner::column_wpc_host(c.kp0);
+    int best = 1;
+    size_t best_waves = 0;
+    for (int cw = 1; cw * wpc <= 8; ++cw) {
+      const size_t wg = shared_max + cw * wave_max;
+      if (wg > 160 * 1024) break;
+      const size_t waves = cw * wpc * ((160 * 1024) / wg);
+      if (waves > best_waves) {
+        best_waves = waves;
+        best = cw;
+      }
+    }
+    c.cpw = best;
+    c.smem = shared_max + best * wave_max;
+  }
+  bp->ncounters = nedner::ST_COUNT + int(bp->col_classes.size());
   // workspace slices
   size_t off = 0;
   for (auto* sp : bp->subs) {
@@ -1044,7 +1077,7 @@ nedner_status create_batch(const nedner_desc* descs, int count, int device, nedn
     }
   }
   DevAlloc A;
-  std::vector<int> zeros(nedner::ST_COUNT, 0);
+  std::vector<int> zeros(bp->ncounters, 0);
   bp->d_counters = static_cast<int*>(const_cast<void*>(A.upload(zeros)));
   if (A.err == hipSuccess) {
     void* q = nullptr;
@@ -1099,7 +1132,7 @@ nedner_status execute_many_impl(nedner_plan plan, const void* const* d_g, void* 
       ch.g[i] = d_g[first + i];
       ch.out[i] = d_out[first + i];
     }
-    NEDNER_RUN(nedner::launch_batch_prepare(plan->d_bp, ch, plan->d_counters, first == 0 ? nedner::ST_COUNT : 0, s),
+    NEDNER_RUN(nedner::launch_batch_prepare(plan->d_bp, ch, plan->d_counters, first == 0 ? plan->ncounters : 0, s),
                "batch prepare");
   }
   auto wl = [&](int st) {
@@ -1115,8 +1148,12 @@ nedner_status execute_many_impl(nedner_plan plan, const void* const* d_g, void* 
   NEDNER_RUN(nedner::launch_pass_many(k0, nedner::ST_LAT_B, plan->d_bp, wl(nedner::ST_LAT_B),
                                       plan->pass_smem[nedner::ST_LAT_B], s), "batched lateral FFT");
   NEDNER_RUN(mk.mark(), "event");
-  NEDNER_RUN(nedner::launch_column_many(k0, plan->d_bp, wl(nedner::ST_COLUMN), plan->col_cpw, plan->col_smem, s),
-             "batched NER column");
+  for (size_t ci = 0; ci < plan->col_classes.size(); ++ci) {
+    const auto& c = plan->col_classes[ci];
+    const nedner::WorkList cl{plan->d_items + plan->stage_off[nedner::ST_COLUMN] + c.off, c.total,
+                              plan->d_counters + nedner::ST_COUNT + ci};
+    NEDNER_RUN(nedner::launch_column_many(c.kp0, plan->d_bp, cl, c.cpw, c.smem, s), "batched NER column");
+  }
   NEDNER_RUN(mk.mark(), "event");
   NEDNER_RUN(nedner::launch_pass_many(k0, nedner::ST_PASS_C, plan->d_bp, wl(nedner::ST_PASS_C),
                                       plan->pass_smem[nedner::ST_PASS_C], s), "batched inverse FFT");
@@ -1181,22 +1218,34 @@ nedner_status set_spread_shape(nedner_plan p, int S, int TT, int PD) {
 }
 
 // Work lists of a batch: per stage, the problems in decreasing order of
-// their block count, each problem's blocks consecutive.
+// their block count, each problem's blocks consecutive; the column stage's
+// list is the concatenation of its classes' lists, each ordered the same way.
 nedner_status batch_build_lists(nedner_plan bp) {
   std::vector<int2> items;
   const int count = int(bp->subs.size());
-  for (int st = 0; st < nedner::ST_COUNT; ++st) {
+  auto append = [&](const std::vector<int>& probs, int st, int cpw) {
     std::vector<std::pair<size_t, int>> order;
-    size_t lds = 0;
-    for (int i = 0; i < count; ++i) {
-      order.push_back({stage_blocks(bp->subs[i]->kp, st, bp->col_cpw), i});
-      lds = std::max(lds, pass_lds(bp->subs[i]->kp, st));
-    }
+    for (int i : probs) order.push_back({stage_blocks(bp->subs[i]->kp, st, cpw), i});
     std::stable_sort(order.begin(), order.end(),
                      [](const std::pair<size_t, int>& a, const std::pair<size_t, int>& b) { return a.first > b.first; });
-    bp->stage_off[st] = int(items.size());
     for (auto& o : order)
       for (size_t b = 0; b < o.first; ++b) items.push_back(make_int2(o.second, int(b)));
+  };
+  std::vector<int> all(count);
+  for (int i = 0; i < count; ++i) all[i] = i;
+  for (int st = 0; st < nedner::ST_COUNT; ++st) {
+    size_t lds = 0;
+    for (int i = 0; i < count; ++i) lds = std::max(lds, pass_lds(bp->subs[i]->kp, st));
+    bp->stage_off[st] = int(items.size());
+    if (st == nedner::ST_COLUMN) {
+      for (auto& c : bp->col_classes) {
+        c.off = int(items.size()) - bp->stage_off[st];
+        append(c.members, st, c.cpw);
+        c.total = int(items.size()) - bp->stage_off[st] - c.off;
+      }
+    } else {
+      append(all, st, 1);
+    }
     bp->stage_total[st] = int(items.size()) - bp->stage_off[st];
     bp->pass_smem[st] = lds;
   }
@@ -1361,7 +1410,7 @@ nedner_status autotune_batch(nedner_plan bp, hipStream_t s, nedner_tuning* out) 
         ch.g[i] = gz[first + i];
         ch.out[i] = oz[first + i];
       }
-      hipError_t e = nedner::launch_batch_prepare(bp->d_bp, ch, bp->d_counters, first == 0 ? nedner::ST_COUNT : 0, s);
+      hipError_t e = nedner::launch_batch_prepare(bp->d_bp, ch, bp->d_counters, first == 0 ? bp->ncounters : 0, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;

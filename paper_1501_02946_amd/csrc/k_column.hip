@@ -37,6 +37,7 @@ hipError_t launch_column_many(const KP& p0, const BatchProb* bp, const WorkList&
 // host helpers for the batched plan: LDS of one column and of the shared
 // twiddles, wavefronts per column
 int column_wpc_host(const KP& p) { return column_wpc(p.ntt, p.N3); }
+int column_ppt_host(const KP& p) { return column_ppt(p); }
 size_t column_wave_bytes_host(const KP& p) {
   return p.prec == PREC_FP64 ? col_wave_bytes<double>(p.ntt, p.N3, false)
                              : col_wave_bytes<float>(p.ntt, p.N3, false);

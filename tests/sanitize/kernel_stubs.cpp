@@ -52,6 +52,7 @@ hipError_t launch_column_many(const KP&, const BatchProb*, const WorkList&, int,
 }
 size_t column_wave_bytes_host(const KP&) { return 0; }
 int column_wpc_host(const KP&) { return 1; }
+int column_ppt_host(const KP&) { return 4; }
 size_t column_shared_bytes_host(const KP&) { return 0; }
 
 }  // namespace nedner
