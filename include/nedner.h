@@ -176,6 +176,10 @@ typedef struct {
   int32_t pass_lines;      /* FFT passes: lines per workgroup (power of two) */
   int32_t pass_threads;    /* FFT passes: threads per workgroup (64..512, multiple of 64) */
   int32_t pass_inplace;    /* FFT passes: in-place (1) or ping-pong (0) transform */
+  int32_t gather_rows;     /* adjoint gather: first-axis cell rows per sweep segment of the
+                              sweep gather (float plans, w <= 12), or 0: the tile-staged
+                              gather (the only one of FP64 plans and w > 12) */
+  int32_t pad1;
   double ms_spread;        /* autotune: spreading time of the chosen shape, ms */
   double ms_execute;       /* autotune: forward execute time of the chosen shape, ms */
 } nedner_tuning;
@@ -363,12 +367,14 @@ nedner_status nedner_get_tuning(nedner_plan plan, nedner_tuning* tuning);
 nedner_status nedner_set_tuning(nedner_plan plan, const nedner_tuning* tuning);
 
 /* Measure candidate launch shapes with HIP events on `stream` and keep the
-   fastest: sweep length, time samples per lane and pipeline depth of the
-   spreading (timed alone), then the FFT pass shape (timed on a whole
-   forward execute). `d_g` is one data array of the plan's problem (any
-   values; for a batch, NULL: each problem's spreading is timed on its own
-   workspace slice with the batch's samples per lane kept). Needs the
-   workspace. Synchronises the device; allocates a temporary volume. */
+   fastest: sweep length and time samples per lane of the spreading (timed
+   alone), the sweep segment of the adjoint gather (timed alone, on the
+   spread grid), then the FFT pass shape (timed on a whole forward execute).
+   `d_g` is one data array of the plan's problem (any values, never written;
+   for a batch, NULL: the batch's spreading launch is timed on zero data in
+   its workspace slices with the batch's samples per lane kept). Needs the
+   workspace. Synchronises the device; allocates a temporary volume and
+   data array. */
 nedner_status nedner_autotune(nedner_plan plan, const void* d_g, void* stream, nedner_tuning* best);
 
 /* Stage timing with HIP events recorded on the execute stream, for up to

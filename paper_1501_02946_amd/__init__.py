@@ -68,7 +68,12 @@ class tuning_struct(ctypes.Structure):
     _fields_ = [("rows_per_wave", ctypes.c_int32), ("time_per_lane", ctypes.c_int32),
                 ("spread_depth", ctypes.c_int32), ("pass_lines", ctypes.c_int32),
                 ("pass_threads", ctypes.c_int32), ("pass_inplace", ctypes.c_int32),
+                ("gather_rows", ctypes.c_int32), ("pad1", ctypes.c_int32),
                 ("ms_spread", ctypes.c_double), ("ms_execute", ctypes.c_double)]
+
+
+def _tuning_dict(t) -> dict:
+    return {k: getattr(t, k) for k, _ in tuning_struct._fields_ if k != "pad1"}
 
 
 _LIB = None
@@ -341,10 +346,12 @@ class Plan:
     def tuning(self) -> dict:
         t = tuning_struct()
         _check(lib().nedner_get_tuning(self._plan, ctypes.byref(t)))
-        return {k: getattr(t, k) for k, _ in tuning_struct._fields_}
+        return _tuning_dict(t)
 
     def set_tuning(self, tuning: dict):
-        t = tuning_struct(**{k: tuning[k] for k, _ in tuning_struct._fields_ if k in tuning})
+        """Set the launch shape; fields missing from `tuning` keep their current values."""
+        cur = self.tuning
+        t = tuning_struct(**{k: tuning.get(k, cur.get(k, 0)) for k, _ in tuning_struct._fields_ if k != "pad1"})
         with self._torch.cuda.device(self.device):
             _check(lib().nedner_set_tuning(self._plan, ctypes.byref(t)))
         self._refresh_info()
@@ -390,7 +397,7 @@ class Plan:
             _check(lib().nedner_autotune(self._plan, ctypes.c_void_p(g.data_ptr()), self._stream(),
                                          ctypes.byref(t)))
         self._refresh_info()
-        res = {k: getattr(t, k) for k, _ in tuning_struct._fields_}
+        res = _tuning_dict(t)
         table[key] = res
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -483,7 +490,7 @@ class BatchPlan:
         with self._torch.cuda.device(self.device):
             stream = ctypes.c_void_p(self._torch.cuda.current_stream(self.device).cuda_stream)
             _check(lib().nedner_autotune(self._plan, None, stream, ctypes.byref(t)))
-        return {k: getattr(t, k) for k, _ in tuning_struct._fields_}
+        return _tuning_dict(t)
 
     def close(self):
         if getattr(self, "_plan", None) is not None and self._plan.value:

@@ -657,6 +657,7 @@ nedner_status forward_impl(nedner_plan plan, const void* d_g, void* d_out, int k
                            const KP* kp = nullptr);
 nedner_status batch_build_lists(nedner_plan bp);
 size_t stage_blocks(const KP& k, int stage, int cpw);
+bool sweep_gather_ok(const KP& k);
 size_t pass_lds(const KP& k, int stage);
 
 nedner_status hip_fail(nedner_plan p, hipError_t e, const char* where) {
@@ -785,6 +786,28 @@ nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* ou
       return x < y;
     });
     k.gorder = static_cast<const int*>(A.upload(order));
+    // the sweep gather's tables: the sensors of each second-axis cell column
+    // by first-axis cell (a counting sort: index order within a cell)
+    const size_t n1 = size_t(v.n1), n2 = size_t(v.n2);
+    bool in_grid = true;
+    for (int64_t m = 0; m < desc->m && in_grid; ++m)
+      in_grid = G.cell[2 * size_t(m)] >= 0 && size_t(G.cell[2 * size_t(m)]) < n1 &&
+                G.cell[2 * size_t(m) + 1] >= 0 && size_t(G.cell[2 * size_t(m) + 1]) < n2;
+    if (in_grid) {
+      std::vector<int> start(n1 * n2 + 1, 0), colm(size_t(desc->m));
+      for (int64_t m = 0; m < desc->m; ++m)
+        start[size_t(G.cell[2 * size_t(m) + 1]) * n1 + size_t(G.cell[2 * size_t(m)]) + 1]++;
+      for (size_t i = 0; i < n1 * n2; ++i) start[i + 1] += start[i];
+      std::vector<int> beg(n2 * (n1 + 1));
+      for (size_t c2 = 0; c2 < n2; ++c2)
+        for (size_t c1 = 0; c1 <= n1; ++c1) beg[c2 * (n1 + 1) + c1] = start[c2 * n1 + c1];
+      std::vector<int> pos(start.begin(), start.end() - 1);
+      for (int64_t m = 0; m < desc->m; ++m)
+        colm[size_t(pos[size_t(G.cell[2 * size_t(m) + 1]) * n1 + size_t(G.cell[2 * size_t(m)])]++)] = int(m);
+      k.gcolbeg = static_cast<const int*>(A.upload(beg));
+      k.gcolm = static_cast<const int*>(A.upload(colm));
+      k.gS = sweep_gather_ok(k) ? 128 : 0;
+    }
   }
   {
     DevAlloc Lst;
@@ -1266,6 +1289,12 @@ nedner_status batch_build_lists(nedner_plan bp) {
   return NEDNER_OK;
 }
 
+bool sweep_gather_ok(const KP& k) {
+  // a grid row's samples are addressed with 32-bit byte offsets
+  return k.prec != NEDNER_FP64 && k.W <= 12 && k.gcolbeg && k.gcolm && !k.equi &&
+         (int64_t)k.n2 * k.Nt * 4 < (int64_t(1) << 31);
+}
+
 void get_tuning(nedner_plan p, nedner_tuning* t) {
   std::memset(t, 0, sizeof(*t));
   t->rows_per_wave = p->kp.S;
@@ -1274,6 +1303,7 @@ void get_tuning(nedner_plan p, nedner_tuning* t) {
   t->pass_lines = p->kp.pass_lines;
   t->pass_threads = p->kp.pass_threads;
   t->pass_inplace = p->kp.pass_ip;
+  t->gather_rows = p->kp.gS;
 }
 
 bool pass_shape_ok(int lines, int threads) {
@@ -1338,11 +1368,53 @@ nedner_status tune_spread(nedner_plan p, const void* d_g, void* U, hipStream_t s
   return set_spread_shape(p, bS, bT, bP);
 }
 
+// Sweep segment length of the adjoint gather: its launch alone on the spread
+// grid in U (the values do not change the cost), into a scratch data array.
+nedner_status tune_gather(nedner_plan p, const void* U, hipStream_t s) {
+  KP& k = p->kp;
+  if (!sweep_gather_ok(k)) return NEDNER_OK;
+  void* gtmp = nullptr;
+  if (hipMalloc(&gtmp, (size_t)k.M * k.Nt * 4) != hipSuccess) return fail(NEDNER_E_OOM, "autotune: no memory");
+  hipEvent_t a = nullptr, b = nullptr;
+  nedner_status st = NEDNER_OK;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) st = fail(NEDNER_E_HIP, "hipEventCreate failed");
+  int best_rows = k.gS;
+  double best = 1e300;
+  for (int rows : {32, 64, 128, 256, 512}) {
+    if (st != NEDNER_OK) break;
+    if (rows > k.n1 && rows != 32) break;  // one segment per column already
+    k.gS = rows;
+    hipError_t e = nedner::launch_gather(k, U, gtmp, s);
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = nedner::launch_gather(k, U, gtmp, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    if (e != hipSuccess) {
+      st = hip_fail(p, e, "gather autotune");
+      break;
+    }
+    if (t < best) {
+      best = t;
+      best_rows = rows;
+    }
+  }
+  k.gS = best_rows;
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipFree(gtmp);
+  return st;
+}
+
 nedner_status autotune_single(nedner_plan p, const void* d_g, hipStream_t s, nedner_tuning* out) {
   if (!p->ws || p->ws_bytes < p->need_ws) return fail(NEDNER_E_WORKSPACE, "autotune needs the workspace");
   if (!d_g) return fail(NEDNER_E_ARG, "autotune needs a data array");
   double ms_spread = 0;
   nedner_status st = p->kp.equi ? NEDNER_OK : tune_spread(p, d_g, p->ws, s, 0, &ms_spread);
+  if (st != NEDNER_OK) return st;
+  // the grid of the last spreading run is in the workspace: the gather's input
+  st = p->kp.equi ? NEDNER_OK : tune_gather(p, p->ws, s);
   if (st != NEDNER_OK) return st;
   void* vol = nullptr;
   const size_t vb = (size_t)p->kp.N1 * p->kp.N2 * p->kp.N3 * (p->kp.prec == NEDNER_FP64 ? 8 : 4);
@@ -1701,13 +1773,16 @@ nedner_status nedner_set_tuning(nedner_plan plan, const nedner_tuning* t) {
   if (!plan->subs.empty()) return fail(NEDNER_E_UNSUPPORTED, "set_tuning applies to single-problem plans");
   if (plan->broken) return fail(NEDNER_E_STATE, "plan is unusable after an earlier HIP error");
   if (!pass_shape_ok(t->pass_lines, t->pass_threads) || t->spread_depth != 1 ||
-      t->rows_per_wave < 1)
+      t->rows_per_wave < 1 || t->gather_rows < 0)
     return fail(NEDNER_E_ARG, "invalid tuning");
+  if (t->gather_rows > 0 && !sweep_gather_ok(plan->kp))
+    return fail(NEDNER_E_ARG, "the sweep gather takes float plans with w <= 12");
   nedner_status st = set_spread_shape(plan, t->rows_per_wave, t->time_per_lane, t->spread_depth);
   if (st != NEDNER_OK) return st;
   plan->kp.pass_lines = t->pass_lines;
   plan->kp.pass_threads = t->pass_threads;
   plan->kp.pass_ip = t->pass_inplace != 0;
+  plan->kp.gS = t->gather_rows;
   return NEDNER_OK;
 }
 

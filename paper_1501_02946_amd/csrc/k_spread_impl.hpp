@@ -440,6 +440,133 @@ __global__ __launch_bounds__(256) void k_gather(KP p, const R* __restrict__ U, R
   gather_body<W, TT, R, WT, A, KAHAN>(p, blockIdx.x, U, g, vec);
 }
 
+// Transpose of the spreading as a sweep along the first axis, the mirror of
+// the forward sweep: a wavefront owns one second-axis cell column c2 (the
+// sensors whose window starts in it all read the same W grid columns), one
+// segment of first-axis cell rows [S0, S1) and 64 time samples (one per lane,
+// coalesced). It walks the grid rows in order, keeping the last RS rows of its
+// W columns in registers (a ring, every index compile-time by unrolling the
+// walk by RS), and loads each row P = RS - W steps before the first sensor
+// that needs it, so the loads of P rows are in flight while the sensors of
+// earlier rows are summed. A sensor of cell row V is summed P steps after row
+// V + W/2 was loaded: all its W x W taps are then in the ring. Each grid value is loaded once per
+// cell column whose window covers it, from L2 (neighbouring columns share
+// their rows there), and every tap of every sensor is read from registers.
+// The terms are added in the order of the tile-staged gather (the W taps of a
+// row in R, then the W row sums in A, with KAHAN compensated), so both give
+// the same values.
+template <int W, int RS, typename R, typename WT, typename A, bool KAHAN>
+__global__ __launch_bounds__(256) void k_gather_sweep(KP p, const int* __restrict__ colbeg,
+                                                      const int* __restrict__ colm,
+                                                      const WT* __restrict__ w1t,
+                                                      const WT* __restrict__ w2t,
+                                                      const R* __restrict__ U, R* __restrict__ g) {
+  constexpr int P = RS - W;
+  static_assert(P >= 0, "the ring holds at least the W rows of a sensor");
+  const int n1 = p.n1, n2 = p.n2, Nt = p.Nt;
+  const int ngrp = (n2 + 3) >> 2;
+  const int nsg = (n1 + p.gS - 1) / p.gS;
+  const int nch = (Nt + 63) >> 6;
+  const int G = ngrp * nsg * nch;
+  // XCD-aware order: each XCD takes a contiguous run of items, column groups
+  // fastest, so that neighbouring cell columns (which read mostly the same
+  // grid columns) sweep the same rows on one XCD at about the same time
+  const int per = (G + 7) >> 3;
+  const int L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (L >= G) return;
+  const int grp = L % ngrp;
+  const int rest = L / ngrp;
+  const int sg = rest % nsg;
+  const int chunk = rest / nsg;
+  const int lane = threadIdx.x & 63;
+  const int c2 = __builtin_amdgcn_readfirstlane(grp * 4 + (threadIdx.x >> 6));
+  if (c2 >= n2) return;
+  const int S0 = sg * p.gS;
+  const int S1 = S0 + p.gS < n1 ? S0 + p.gS : n1;
+  const int t = chunk * 64 + lane;
+  const bool tok = t < Nt;
+  // lanes past the end read sample 0 (a valid address) and store nothing
+  const unsigned toff = tok ? unsigned(t) : 0u;
+  const int* __restrict__ cb = colbeg + (size_t)c2 * (n1 + 1);
+  // rows are read with buffer loads: a scalar resource per grid row (its
+  // n2 Nt samples), a scalar byte offset per column and one vector byte
+  // offset for the lane, so that no load needs a 64-bit vector address
+  static_assert(sizeof(R) == 4, "the sweep gather reads 32-bit samples");
+  const int rowbytes = n2 * Nt * 4;
+  const int voff = int(toff) * 4;
+  int soff[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) soff[k] = pmod(c2 - W / 2 + 1 + k, n2) * Nt * 4;
+  R ring[RS][W];
+  const int Qa = S0 - W / 2 + 1, Qb = S1 - 1 + W / 2;
+  int e = cb[S0];
+  for (int q0 = floor_div(Qa, RS) * RS; q0 <= Qb + P; q0 += RS) {
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      const int q1 = q0 + r;
+      if (q1 < Qa || q1 > Qb + P) continue;
+      // first the sensors whose last row is q1 - P (the newest of their rows
+      // was loaded P steps ago), then the loads of row q1 into the slot of
+      // row q1 - RS, which no sensor needs any more
+      const int V = q1 - P - W / 2;
+      if (V >= S0 && V < S1) {
+        const int e_end = cb[V + 1];
+        for (; e < e_end; ++e) {
+          const int m = __builtin_amdgcn_readfirstlane(colm[e]);
+          const WT* __restrict__ w1 = w1t + (size_t)m * W;
+          const WT* __restrict__ w2 = w2t + (size_t)m * W;
+          A acc = A(0), cmp = A(0);
+#pragma unroll
+          for (int k1 = 0; k1 < W; ++k1) {
+            // row V - W/2 + 1 + k1 = q1 - RS + 1 + k1 sits in slot (r + 1 + k1) mod RS
+            const int sl = (r + 1 + k1) % RS;
+            R ra = R(0);
+#pragma unroll
+            for (int k2 = 0; k2 < W; ++k2) ra += R(w2[k2]) * ring[sl][k2];
+            const A wk = A(w1[k1]);
+            if constexpr (KAHAN) {
+              const A y = fmaf(wk, A(ra), -cmp);
+              const A s2 = acc + y;
+              cmp = (s2 - acc) - y;
+              acc = s2;
+            } else {
+              acc += wk * A(ra);
+            }
+          }
+          if (tok) g[(size_t)m * Nt + t] = KAHAN ? R(acc - cmp) : R(acc);
+        }
+      }
+      if (q1 <= Qb) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<R*>(U + (size_t)pmod(q1, n1) * n2 * Nt), (short)0, rowbytes, 0x00020000);
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+          ring[r][k] = __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff[k], 0));
+      }
+    }
+  }
+}
+
+// ring rows of the sweep gather: W plus rows loaded ahead (0: no sweep for W)
+template <int W>
+constexpr int sweep_ring() {
+  return W <= 12 ? 16 : 0;
+}
+
+template <typename R, typename WT, typename A, bool KAHAN, int W>
+static hipError_t gather_sweep_w(const KP& p, const void* U, void* g, hipStream_t s) {
+  constexpr int RS = sweep_ring<W>();
+  if constexpr (RS == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    const long G = (long)((p.n2 + 3) / 4) * ((p.n1 + p.gS - 1) / p.gS) * ((p.Nt + 63) / 64);
+    hipLaunchKernelGGL((k_gather_sweep<W, RS, R, WT, A, KAHAN>), dim3(unsigned(8 * ((G + 7) / 8))), dim3(256), 0, s,
+                       p, p.gcolbeg, p.gcolm, static_cast<const WT*>(p.w1), static_cast<const WT*>(p.w2),
+                       static_cast<const R*>(U), static_cast<R*>(g));
+    return hipGetLastError();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // dispatch over (precision, W, TT)
 
@@ -479,8 +606,27 @@ static hipError_t spread_w(const KP& p, const void* g, void* U, int vec, hipStre
   }
 }
 
+// The sweep gather where it applies: float data (the ring of double values
+// would not fit the registers), tables present, W <= 12.
+inline bool use_sweep_gather(const KP& p, size_t rsize) {
+  return rsize == 4 && p.gS > 0 && p.gcolbeg && p.gcolm && p.W <= 12;
+}
+
 template <typename R, typename WT, typename A, bool KAHAN>
 hipError_t spread_p(const KP& p, const void* a, void* b, int vec, hipStream_t s, bool adj) {
+  if constexpr (sizeof(R) == 4) {
+    if (adj && use_sweep_gather(p, sizeof(R))) {
+      switch (p.W) {
+        case 2: return gather_sweep_w<R, WT, A, KAHAN, 2>(p, a, b, s);
+        case 4: return gather_sweep_w<R, WT, A, KAHAN, 4>(p, a, b, s);
+        case 6: return gather_sweep_w<R, WT, A, KAHAN, 6>(p, a, b, s);
+        case 8: return gather_sweep_w<R, WT, A, KAHAN, 8>(p, a, b, s);
+        case 10: return gather_sweep_w<R, WT, A, KAHAN, 10>(p, a, b, s);
+        case 12: return gather_sweep_w<R, WT, A, KAHAN, 12>(p, a, b, s);
+        default: return hipErrorInvalidValue;
+      }
+    }
+  }
   switch (p.W) {
     case 2: return spread_w<R, WT, A, KAHAN, 2>(p, a, b, vec, s, adj);
     case 4: return spread_w<R, WT, A, KAHAN, 4>(p, a, b, vec, s, adj);

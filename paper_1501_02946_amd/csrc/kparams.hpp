@@ -65,6 +65,10 @@ struct KP {
   const int* node;     // equispaced: [n1 * n2] sensor at each node, -1 where none
   const int* gorder;   // [M] the sensors in the order the adjoint gather takes them: by tiles
                        // of 4 x 4 grid cells, so that consecutive sensors are neighbours
+  const int* gcolbeg;  // [n2][n1 + 1] sweep gather: start of cell (c1, c2) in gcolm, per
+                       // second-axis cell c2, c1 = 0..n1 (c1 = n1: end of the column)
+  const int* gcolm;    // [M] sweep gather: the sensors by (c2, c1), index order within a cell
+  int gS;              // sweep gather: first-axis cell rows per sweep segment (0: no sweep tables)
   const void* sw;      // equispaced: [M] real: h_m / (d1 d2)
   const void* dec1;    // [J1] real: 1/phihat_1(j1), j1 = -N1/2..N1/2
   const void* dec2;    // [K2] real: 1/phihat_2(k2), k2 = 0..N2/2
