@@ -80,7 +80,7 @@ typedef enum {
   NEDNER_FP32_COMPENSATED = 2,  /* as FP32, with compensated float sums where many terms meet:
                                    the spreading holds each grid value as a pair hi + lo of
                                    floats, adds terms to lo and folds lo into hi with Kahan's
-                                   update after every 8 terms (blocked compensated summation),
+                                   update after every 16 terms (blocked compensated summation),
                                    rounding hi + lo once; the adjoint gather adds its W row
                                    sums with Kahan's update */
   NEDNER_FP32_PLAIN = 3,        /* float everywhere, arguments included */

@@ -149,7 +149,7 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
   static_assert(!KAHAN || sizeof(A) == 4, "the compensated sums are float");
   // acc: the sums (plain), or the low parts lo (KAHAN); hi: the high parts
   constexpr int KW = KAHAN ? W : 1, KT = KAHAN ? TT : 1;
-  constexpr int FOLD = 8;
+  constexpr int FOLD = 16;
   int since_fold = 0;
   A acc[W][TT];
   A hi[KW][KT];
