@@ -364,7 +364,11 @@ def leg_precision(torch, N, p, prec, a, flags=(), tuning=None, **kw):
     the plan's default); returns (record, volume on the host)."""
     plan = make_plan(N, p, prec, flags=list(flags), **kw)
     if tuning:
-        plan.set_tuning(tuning)
+        t = dict(tuning)
+        if plan.tuning["gather_rows"] == 0:
+            # FP64 plans and wide windows take the tile-staged gather only
+            t["gather_rows"] = 0
+        plan.set_tuning(t)
     g = torch.as_tensor(p.g, dtype=plan.dtype, device=plan.device).contiguous()
     out = torch.empty((p.n1, p.n2, p.n3), dtype=plan.dtype, device=plan.device)
     ms, _ = time_op(torch, plan, lambda: plan.forward(g, out=out), a.steps, a.warmup)

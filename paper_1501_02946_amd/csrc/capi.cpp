@@ -285,11 +285,16 @@ nedner_status validate_impl(const nedner_desc* d, Derived* out) {
   v.TT = TT;
   v.nchunk = int((d->nt + 64 * TT - 1) / (64 * TT));
   int S = d->rows_per_wave;
-  // mean sweep length n1/4, at least 4W: shorter sweeps spend much of their
-  // work on the W-1 warm-up cells, longer ones leave too few wavefronts to
-  // hide the load latency (measured on the 128^2 x 512 and 256^2 x 1024
+  // default mean sweep length: as long as the launch still has about 1024
+  // workgroups (four per CU) to spread over the chip, between 2W and
+  // max(4W, n1/4): shorter sweeps spend much of their work on the W-1 warm-up
+  // cells, longer ones leave too few wavefronts to hide the load latency
+  // (measured on the 128^2 x 512, 256^2 x 1024 and 1024-sensor line
   // workloads; the autotuner refines it)
-  if (S == 0) S = int(std::max<long>(4L * v.W, v.n1 / 4));
+  if (S == 0) {
+    const long fill = long(v.n1) * ((v.n2 + 3) / 4) * v.nchunk / 1024;
+    S = int(std::min<long>(std::max<long>(fill, 2L * v.W), std::max<long>(4L * v.W, v.n1 / 4)));
+  }
   S = int(std::min<long>(S, v.n1));
   v.S = S;
   v.nseg = int((v.n1 + S - 1) / S);
