@@ -235,11 +235,13 @@ __device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, 
 // PPT * nth), which fixes the register array of every stage at compile time:
 // a thread holds ceil(PPT / R) butterflies of radix R. Caller synchronises
 // before; the result is in `buf` and visible on return.
+// s0, Ns0: start at stage s0 with Ns0 the product of the radices before it
+// (the earlier stages done by the caller, see stage_first_ip).
 template <bool INV, typename T, bool WAVE, int PPT>
 __device__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, int ls, const cpx<T>* tw,
-                           int tid, int nth) {
-  int Ns = 1;
-  for (int s = 0; s < rd.count; ++s) {
+                           int tid, int nth, int s0 = 0, int Ns0 = 1) {
+  int Ns = Ns0;
+  for (int s = s0; s < rd.count; ++s) {
     const int R = rd.r[s];
     switch (R) {
       case 2: stage_ip<2, (PPT + 1) / 2, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
@@ -249,6 +251,32 @@ __device__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, in
       default: stage_ip<8, (PPT + 7) / 8, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
     }
     Ns *= R;
+  }
+}
+
+// The first Stockham stage (Ns = 1) of a single line of length n with radix
+// R, its inputs taken from f(i) (typically global loads) instead of LDS: the
+// line never has to be staged in LDS before the transform. Butterfly j reads
+// points j + r n/R, r < R, and writes its outputs to buf[j R + r]. K
+// butterflies per thread (K * nth >= n / R). The caller synchronises after.
+template <int R, int K, typename T, typename F>
+__device__ __forceinline__ void stage_first_ip(cpx<T>* buf, int n, int tid, int nth, F&& f) {
+  const int nb = n / R;
+  cpx<T> v[K][R];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int j = tid + q * nth;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[q][r] = j < nb ? f(j + r * nb) : cpx<T>{T(0), T(0)};
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int j = tid + q * nth;
+    if (j < nb) {
+      dft_small<R, false>(v[q]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[j * R + r] = v[q][r];
+    }
   }
 }
 

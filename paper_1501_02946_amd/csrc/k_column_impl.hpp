@@ -322,14 +322,23 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
     for (int i = ct; i < N3; i += CN) z1[i] = cpx<R>{R(0), R(0)};
   }
   const cpx<R>* gc = G + col * Nt;
-  stage_in<(PPT < 16 ? PPT : 16)>(sm.a, ntt, ct, CN, [&](int s) {
-    // slot s holds n' = s (s < ntt/2) or s - ntt; data index n = n' + Nt/2
+  // slot s of the padded line holds n' = s (s < ntt/2) or s - ntt; data index n = n' + Nt/2
+  auto sample = [&](int s) {
     const int np = s < ntt / 2 ? s : s - ntt;
     const int n = np + Nt / 2;
     return (act && n >= 0 && n < Nt) ? gc[n] : cpx<R>{R(0), R(0)};
-  });
-  sync_policy<WV>();
-  fft_lds_ip<false, R, WV, PPT>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, ct, CN);
+  };
+  if (p.r_ntt.r[0] == 8) {
+    // the first radix-8 stage straight from global memory: the samples go
+    // from the loads into the butterflies, not through LDS first
+    stage_first_ip<8, (PPT + 7) / 8>(sm.a, ntt, ct, CN, sample);
+    sync_policy<WV>();
+    fft_lds_ip<false, R, WV, PPT>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, ct, CN, 1, 8);
+  } else {
+    stage_in<(PPT < 16 ? PPT : 16)>(sm.a, ntt, ct, CN, sample);
+    sync_policy<WV>();
+    fft_lds_ip<false, R, WV, PPT>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, ct, CN);
+  }
   const cpx<R>* B = sm.a;
   if (ct < W) sm.a[ntt + ct] = sm.a[ct];
   sync_policy<WV>();
