@@ -187,10 +187,21 @@ __device__ __forceinline__ void sync_policy() {
     __syncthreads();
 }
 
+// Swizzled layout of a single line (lines = 1, ps = 1): point i at
+// i ^ ((i >> 4) & 7), a permutation within each block of 16 points (128
+// bytes of complex float: the 32 LDS banks). The first radix-8 stage writes
+// each butterfly's outputs to 8 consecutive points, so the lanes of a
+// wavefront write 64 bytes apart: in the plain layout 16 lanes fall on the
+// same 2 bank pairs (an 8-way conflict); the swizzle gives each of them its
+// own pair, and 16 consecutive points aligned to 16 stay on 16 distinct pairs.
+// The footprint is unchanged (no LDS is added).
+__device__ __forceinline__ int swz(int i) { return i ^ ((i >> 4) & 7); }
+
 // `lines` is a power of two; Ns (the product of the radices already done) is
 // one for power-of-two lengths, so the index arithmetic is shifts and masks
 // there and true divisions only for lengths with factors 3 or 5.
-template <int R, int K, bool INV, typename T, bool WAVE = false>
+// PIN, POUT: the stage reads / writes the swizzled layout (single lines only).
+template <int R, int K, bool INV, typename T, bool WAVE = false, bool PIN = false, bool POUT = false>
 __device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, int ps, int ls,
                                          const cpx<T>* __restrict__ tw, int tid, int nth) {
   const int nb = n / R;
@@ -205,7 +216,8 @@ __device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, 
     if (t < total) {
       const int b = t & (lines - 1), j = t >> lsh;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * nb) * ps + b * ls];
+      for (int r = 0; r < R; ++r)
+        v[q][r] = PIN ? buf[swz(j + r * nb)] : buf[(j + r * nb) * ps + b * ls];
     }
   }
   sync_policy<WAVE>();
@@ -225,7 +237,12 @@ __device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, 
       dft_small<R, INV>(v[q]);
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(base + r * Ns) * ps + b * ls] = v[q][r];
+      for (int r = 0; r < R; ++r) {
+        if constexpr (POUT)
+          buf[swz(base + r * Ns)] = v[q][r];
+        else
+          buf[(base + r * Ns) * ps + b * ls] = v[q][r];
+      }
     }
   }
   sync_policy<WAVE>();
@@ -237,19 +254,28 @@ __device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, 
 // before; the result is in `buf` and visible on return.
 // s0, Ns0: start at stage s0 with Ns0 the product of the radices before it
 // (the earlier stages done by the caller, see stage_first_ip).
-template <bool INV, typename T, bool WAVE, int PPT>
+// PAD (single lines only): the line arrives in the swizzled layout and every
+// stage but the last keeps it; the last writes the plain layout.
+template <bool INV, typename T, bool WAVE, int PPT, bool PAD = false>
 __device__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, int ls, const cpx<T>* tw,
                            int tid, int nth, int s0 = 0, int Ns0 = 1) {
   int Ns = Ns0;
   for (int s = s0; s < rd.count; ++s) {
     const int R = rd.r[s];
+    const bool last = s + 1 == rd.count;
+#define NEDNER_STAGE(RR)                                                                                  \
+  if (PAD && !last)                                                                                       \
+    stage_ip<RR, (PPT + RR - 1) / RR, INV, T, WAVE, PAD, PAD>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); \
+  else                                                                                                    \
+    stage_ip<RR, (PPT + RR - 1) / RR, INV, T, WAVE, PAD, false>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth);
     switch (R) {
-      case 2: stage_ip<2, (PPT + 1) / 2, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
-      case 3: stage_ip<3, (PPT + 2) / 3, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
-      case 4: stage_ip<4, (PPT + 3) / 4, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
-      case 5: stage_ip<5, (PPT + 4) / 5, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
-      default: stage_ip<8, (PPT + 7) / 8, INV, T, WAVE>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); break;
+      case 2: NEDNER_STAGE(2) break;
+      case 3: NEDNER_STAGE(3) break;
+      case 4: NEDNER_STAGE(4) break;
+      case 5: NEDNER_STAGE(5) break;
+      default: NEDNER_STAGE(8) break;
     }
+#undef NEDNER_STAGE
     Ns *= R;
   }
 }
@@ -257,9 +283,10 @@ __device__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, in
 // The first Stockham stage (Ns = 1) of a single line of length n with radix
 // R, its inputs taken from f(i) (typically global loads) instead of LDS: the
 // line never has to be staged in LDS before the transform. Butterfly j reads
-// points j + r n/R, r < R, and writes its outputs to buf[j R + r]. K
-// butterflies per thread (K * nth >= n / R). The caller synchronises after.
-template <int R, int K, typename T, typename F>
+// points j + r n/R, r < R, and writes its outputs to point j R + r (of the
+// swizzled layout with POUT). K butterflies per thread (K * nth >= n / R). The
+// caller synchronises after.
+template <int R, int K, bool POUT, typename T, typename F>
 __device__ __forceinline__ void stage_first_ip(cpx<T>* buf, int n, int tid, int nth, F&& f) {
   const int nb = n / R;
   cpx<T> v[K][R];
@@ -275,7 +302,7 @@ __device__ __forceinline__ void stage_first_ip(cpx<T>* buf, int n, int tid, int 
     if (j < nb) {
       dft_small<R, false>(v[q]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[j * R + r] = v[q][r];
+      for (int r = 0; r < R; ++r) buf[POUT ? swz(j * R + r) : j * R + r] = v[q][r];
     }
   }
 }

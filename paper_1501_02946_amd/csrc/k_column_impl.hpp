@@ -257,9 +257,13 @@ __host__ __device__ inline bool col_fl_in_regs(int N3) { return N3 + 1 <= 64 * N
 // worth of LDS. Shared by the single and the batched launches.
 __host__ __device__ inline int column_wpc(int ntt, int N3) { return (ntt > N3 ? ntt : N3) > 512 ? 4 : 1; }
 
+// Points of a column's transform buffer: the longer transform and the tap
+// extension.
+__host__ __device__ inline int col_nbuf(int ntt, int N3) { return (ntt > N3 ? ntt : N3) + COL_EXT; }
+
 template <typename R>
 __host__ __device__ inline size_t col_wave_bytes(int ntt, int N3, bool adj) {
-  const size_t nbuf = (ntt > N3 ? ntt : N3) + COL_EXT;
+  const size_t nbuf = col_nbuf(ntt, N3);
   size_t b = sizeof(cpx<R>) * nbuf;
   if (adj || !col_fl_in_regs(N3))
     b += (sizeof(cpx<R>) + sizeof(R) + sizeof(int)) * ((size_t)N3 + 2);
@@ -275,7 +279,7 @@ __host__ __device__ inline size_t col_shared_bytes(int ntt, int N3) {
 template <typename R>
 __device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int column, bool adj) {
   ColSmem<R> s;
-  const int nbuf = (p.ntt > p.N3 ? p.ntt : p.N3) + COL_EXT;
+  const int nbuf = col_nbuf(p.ntt, p.N3);
   s.twt = reinterpret_cast<cpx<R>*>(smem);
   s.tw3 = s.twt + p.ntt;
   char* w = smem + col_shared_bytes<R>(p.ntt, p.N3) + (size_t)column * col_wave_bytes<R>(p.ntt, p.N3, adj);
@@ -328,12 +332,14 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
     const int n = np + Nt / 2;
     return (act && n >= 0 && n < Nt) ? gc[n] : cpx<R>{R(0), R(0)};
   };
-  if (p.r_ntt.r[0] == 8) {
+  if (p.r_ntt.r[0] == 8 && ntt % 128 == 0) {
     // the first radix-8 stage straight from global memory: the samples go
-    // from the loads into the butterflies, not through LDS first
-    stage_first_ip<8, (PPT + 7) / 8>(sm.a, ntt, ct, CN, sample);
+    // from the loads into the butterflies, not through LDS first; the
+    // stages keep the swizzled layout (swz) until the last, which writes
+    // the plain one the gather reads
+    stage_first_ip<8, (PPT + 7) / 8, true>(sm.a, ntt, ct, CN, sample);
     sync_policy<WV>();
-    fft_lds_ip<false, R, WV, PPT>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, ct, CN, 1, 8);
+    fft_lds_ip<false, R, WV, PPT, true>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, ct, CN, 1, 8);
   } else {
     stage_in<(PPT < 16 ? PPT : 16)>(sm.a, ntt, ct, CN, sample);
     sync_policy<WV>();
