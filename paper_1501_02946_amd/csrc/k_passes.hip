@@ -355,26 +355,39 @@ __device__ __forceinline__ void adj_a_body(const KP& p, int TB, int bx, int by, 
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_n2), n, tid, nth);
   const cpx<R>* src = V + (size_t)q1 * p.K2 * p.Nt;
   const int lsh = __builtin_ctz(TB);
-  stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
-    const int k = i >> lsh, pr = pb + (i & (TB - 1));
-    cpx<R> c = {R(0), R(0)};
-    if (pr < npairs) {
-      if (k == 0 || (k == h2 && 2 * h2 == n)) {
-        // real bins (k = 0, and the Nyquist bin n/2 when it is kept, n = N2):
-        // the two half-spectrum terms of the forward fall on one bin
-        const cpx<R> a = src[(size_t)k * p.Nt + 2 * pr], b = src[(size_t)k * p.Nt + 2 * pr + 1];
-        c = {a.x, b.x};
-      } else if (k <= h2) {
-        const cpx<R> a = src[(size_t)k * p.Nt + 2 * pr], b = src[(size_t)k * p.Nt + 2 * pr + 1];
-        c = {(a.x - b.y) * R(0.5), (a.y + b.x) * R(0.5)};
-      } else if (k >= n - h2) {
-        const int kk = n - k;
-        const cpx<R> a = src[(size_t)kk * p.Nt + 2 * pr], b = src[(size_t)kk * p.Nt + 2 * pr + 1];
-        c = {(a.x + b.y) * R(0.5), (b.x - a.y) * R(0.5)};
+  // bins between the two kept halves (oversampled grid) hold no mode
+  const int nmid = n - 2 * h2 - 1;
+  for (int i = tid; i < nmid * TB; i += nth) sm.a[(h2 + 1) * TB + i] = cpx<R>{R(0), R(0)};
+  // each half-spectrum bin k = 0..h2 is read once and feeds bins k and n - k:
+  // the real bins (k = 0, and the Nyquist bin n/2 when it is kept, n = N2)
+  // take the two half-spectrum terms of the forward on one bin
+  constexpr int BATCH = 4;
+  const int total = (h2 + 1) * TB;
+  for (int base = 0; base < total; base += BATCH * nth) {
+    cpx<R> a[BATCH], b[BATCH];
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int i = base + tid + q * nth;
+      const int k = i >> lsh, pr = pb + (i & (TB - 1));
+      a[q] = b[q] = cpx<R>{R(0), R(0)};
+      if (i < total && pr < npairs) {
+        a[q] = src[(size_t)k * p.Nt + 2 * pr];
+        b[q] = src[(size_t)k * p.Nt + 2 * pr + 1];
       }
     }
-    return c;
-  });
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int i = base + tid + q * nth;
+      if (i >= total) continue;
+      const int k = i >> lsh, pp = i & (TB - 1);
+      if (k == 0 || (k == h2 && 2 * h2 == n)) {
+        sm.a[k * TB + pp] = cpx<R>{a[q].x, b[q].x};
+      } else {
+        sm.a[k * TB + pp] = cpx<R>{(a[q].x - b[q].y) * R(0.5), (a[q].y + b[q].x) * R(0.5)};
+        sm.a[(n - k) * TB + pp] = cpx<R>{(a[q].x + b[q].y) * R(0.5), (b[q].x - a[q].y) * R(0.5)};
+      }
+    }
+  }
   __syncthreads();
   cpx<R>* Z = pass_fft<true, R, IP>(sm, p.r_n2, TB, tid, nth);
   R* dst = U + (size_t)q1 * n * p.Nt;
