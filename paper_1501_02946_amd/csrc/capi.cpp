@@ -167,7 +167,8 @@ size_t column_lds(const nedner_desc& d, const Derived& v) {
   const size_t rs = real_size(d.prec), cs = 2 * rs;
   const size_t nbuf = std::max<size_t>(v.ntt, d.n3) + nedner::COL_EXT;
   const size_t wave = (cs * (nbuf + d.n3 + 1) + (rs + 4) * (d.n3 + 1) + 15) & ~size_t(15);
-  return cs * (v.ntt + d.n3) + wave;
+  // half-period twiddle tables; the depth table shares the time table when n3 divides ntt
+  return cs * (v.ntt / 2 + (v.ntt % d.n3 ? d.n3 / 2 : 0)) + wave;
 }
 
 // Node (i1, i2) of sensor m when it sits on the output grid a + i d (after

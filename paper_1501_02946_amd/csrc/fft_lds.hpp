@@ -49,6 +49,25 @@ struct Radices {
   int r[16];
 };
 
+// Twiddle lookup: a full table tw[i] = exp(-2 pi i / n) (a plain pointer), or
+// the first half of one (TwHalf: tw[i + n/2] = -tw[i]) read at index i * mul,
+// so that a length-n/mul transform can use the table of a length-n one.
+template <typename T>
+struct TwHalf {
+  const cpx<T>* t;
+  int mul;  // index stride into the table
+  int nh;   // entries held: half the table's length
+};
+template <typename T>
+__device__ __forceinline__ cpx<T> twget(const cpx<T>* tw, int i) { return tw[i]; }
+template <typename T>
+__device__ __forceinline__ cpx<T> twget(const TwHalf<T>& tw, int i) {
+  const int ii = i * tw.mul;
+  if (ii < tw.nh) return tw.t[ii];
+  const cpx<T> w = tw.t[ii - tw.nh];
+  return cpx<T>{-w.x, -w.y};
+}
+
 template <int R, bool INV, typename T>
 __device__ __forceinline__ void dft_small(cpx<T>* v) {
   if constexpr (R == 2) {
@@ -201,9 +220,10 @@ __device__ __forceinline__ int swz(int i) { return i ^ ((i >> 4) & 7); }
 // one for power-of-two lengths, so the index arithmetic is shifts and masks
 // there and true divisions only for lengths with factors 3 or 5.
 // PIN, POUT: the stage reads / writes the swizzled layout (single lines only).
-template <int R, int K, bool INV, typename T, bool WAVE = false, bool PIN = false, bool POUT = false>
+template <int R, int K, bool INV, typename T, bool WAVE = false, bool PIN = false, bool POUT = false,
+          typename TWT = const cpx<T>*>
 __device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, int ps, int ls,
-                                         const cpx<T>* __restrict__ tw, int tid, int nth) {
+                                         const TWT& tw, int tid, int nth) {
   const int nb = n / R;
   const int total = nb * lines;
   const int tstep = n / (Ns * R);
@@ -230,7 +250,7 @@ __device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, 
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cpx<T> w = tw[r * k * tstep];
+          cpx<T> w = twget(tw, r * k * tstep);
           v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
         }
       }
@@ -256,8 +276,8 @@ __device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, 
 // (the earlier stages done by the caller, see stage_first_ip).
 // PAD (single lines only): the line arrives in the swizzled layout and every
 // stage but the last keeps it; the last writes the plain layout.
-template <bool INV, typename T, bool WAVE, int PPT, bool PAD = false>
-__device__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, int ls, const cpx<T>* tw,
+template <bool INV, typename T, bool WAVE, int PPT, bool PAD = false, typename TWT = const cpx<T>*>
+__device__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, int ls, const TWT& tw,
                            int tid, int nth, int s0 = 0, int Ns0 = 1) {
   int Ns = Ns0;
   for (int s = s0; s < rd.count; ++s) {
@@ -265,9 +285,11 @@ __device__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, in
     const bool last = s + 1 == rd.count;
 #define NEDNER_STAGE(RR)                                                                                  \
   if (PAD && !last)                                                                                       \
-    stage_ip<RR, (PPT + RR - 1) / RR, INV, T, WAVE, PAD, PAD>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth); \
+    stage_ip<RR, (PPT + RR - 1) / RR, INV, T, WAVE, PAD, PAD, TWT>(buf, rd.n, Ns, lines, ps, ls, tw, tid,    \
+                                                                  nth);                                   \
   else                                                                                                    \
-    stage_ip<RR, (PPT + RR - 1) / RR, INV, T, WAVE, PAD, false>(buf, rd.n, Ns, lines, ps, ls, tw, tid, nth);
+    stage_ip<RR, (PPT + RR - 1) / RR, INV, T, WAVE, PAD, false, TWT>(buf, rd.n, Ns, lines, ps, ls, tw, tid,  \
+                                                                    nth);
     switch (R) {
       case 2: NEDNER_STAGE(2) break;
       case 3: NEDNER_STAGE(3) break;

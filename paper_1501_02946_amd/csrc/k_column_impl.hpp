@@ -230,19 +230,24 @@ __device__ __forceinline__ double x_lateral(const KP& p, double a) {
     return double(float(p.cdtnt) * sqrtf(float(a)));
 }
 
-// LDS of one workgroup: the two twiddle tables, shared, then per column the
+// LDS of one workgroup: the twiddle tables, shared, then per column the
 // transform buffer and, unless the forward kernel keeps its per-l values in
-// registers, the per-l arrays.
+// registers, the per-l arrays. The tables hold half a period each
+// (tw[i + n/2] = -tw[i]); the depth transform reads the time transform's
+// table with stride ntt/N3 when N3 divides ntt, else a table of its own.
+// Smaller shared tables leave room for more columns per CU.
 template <typename R>
 struct ColSmem {
-  cpx<R>* twt;  // ntt twiddles
-  cpx<R>* tw3;  // N3 twiddles
-  cpx<R>* a;    // nbuf: the transform buffer (in place)
-  cpx<R>* fl;   // N3 + 2: one value per output l, and the second l = 0 point of Q
-  R* fr;        // N3 + 2 (adjoint)
-  int* q0;      // N3 + 2 (adjoint)
-  int* st;      // ntt + 2 (adjoint): number of points below each grid cell
+  cpx<R>* twt;    // ntt/2 twiddles
+  cpx<R>* tw3;    // N3/2 twiddles (= twt when N3 divides ntt)
+  cpx<R>* a;      // nbuf: the transform buffer (in place)
+  cpx<R>* fl;     // N3 + 2: one value per output l, and the second l = 0 point of Q
+  R* fr;          // N3 + 2 (adjoint)
+  int* q0;        // N3 + 2 (adjoint)
+  short* st;      // ntt + 2 (adjoint): number of points below each grid cell
 };
+
+__host__ __device__ inline bool col_tw3_shared(int ntt, int N3) { return ntt % N3 == 0; }
 
 // The forward kernel holds the N3 + 1 values of a column in registers when
 // they fit (N3 + 1 <= 64 NL_REG, NL_REG per lane with one wavefront per
@@ -267,13 +272,29 @@ __host__ __device__ inline size_t col_wave_bytes(int ntt, int N3, bool adj) {
   size_t b = sizeof(cpx<R>) * nbuf;
   if (adj || !col_fl_in_regs(N3))
     b += (sizeof(cpx<R>) + sizeof(R) + sizeof(int)) * ((size_t)N3 + 2);
-  if (adj) b += sizeof(int) * ((size_t)ntt + 2);
+  if (adj) b += sizeof(short) * ((size_t)ntt + 2);
   return (b + 15) & ~size_t(15);
 }
 
 template <typename R>
 __host__ __device__ inline size_t col_shared_bytes(int ntt, int N3) {
-  return sizeof(cpx<R>) * ((size_t)ntt + N3);
+  const size_t n = (size_t)ntt / 2 + (col_tw3_shared(ntt, N3) ? 0 : (size_t)N3 / 2);
+  return (sizeof(cpx<R>) * n + 15) & ~size_t(15);
+}
+
+// The column's two twiddle accessors and the staging of their tables.
+template <typename R>
+__device__ __forceinline__ void col_twiddles(const ColSmem<R>& sm, const KP& p, int tid, int nth) {
+  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), p.ntt / 2, tid, nth);
+  if (!col_tw3_shared(p.ntt, p.N3)) load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), p.N3 / 2, tid, nth);
+}
+template <typename R>
+__device__ __forceinline__ TwHalf<R> col_twt(const ColSmem<R>& sm, const KP& p) {
+  return TwHalf<R>{sm.twt, 1, p.ntt / 2};
+}
+template <typename R>
+__device__ __forceinline__ TwHalf<R> col_tw3(const ColSmem<R>& sm, const KP& p) {
+  return col_tw3_shared(p.ntt, p.N3) ? TwHalf<R>{sm.twt, p.ntt / p.N3, p.ntt / 2} : TwHalf<R>{sm.tw3, 1, p.N3 / 2};
 }
 
 template <typename R>
@@ -281,13 +302,13 @@ __device__ __forceinline__ ColSmem<R> col_carve(char* smem, const KP& p, int col
   ColSmem<R> s;
   const int nbuf = col_nbuf(p.ntt, p.N3);
   s.twt = reinterpret_cast<cpx<R>*>(smem);
-  s.tw3 = s.twt + p.ntt;
+  s.tw3 = col_tw3_shared(p.ntt, p.N3) ? s.twt : s.twt + p.ntt / 2;
   char* w = smem + col_shared_bytes<R>(p.ntt, p.N3) + (size_t)column * col_wave_bytes<R>(p.ntt, p.N3, adj);
   s.a = reinterpret_cast<cpx<R>*>(w);
   s.fl = s.a + nbuf;
   s.fr = reinterpret_cast<R*>(s.fl + p.N3 + 2);
   s.q0 = reinterpret_cast<int*>(s.fr + p.N3 + 2);
-  s.st = s.q0 + p.N3 + 2;
+  s.st = reinterpret_cast<short*>(s.q0 + p.N3 + 2);
   return s;
 }
 
@@ -309,8 +330,7 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
   const int ct = tid % CN, cw = tid / CN;
   const int ntt = p.ntt, N3 = p.N3, Nt = p.Nt, h3 = N3 / 2;
   ColSmem<R> sm = col_carve<R>(smem, p, cw, false);
-  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
-  load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
+  col_twiddles(sm, p, tid, nth);
   __syncthreads();
   const int cidx = __builtin_amdgcn_readfirstlane(bx * (nth / CN) + cw);
   const bool live = cidx < ncol;
@@ -339,11 +359,11 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
     // the plain one the gather reads
     stage_first_ip<8, (PPT + 7) / 8, true>(sm.a, ntt, ct, CN, sample);
     sync_policy<WV>();
-    fft_lds_ip<false, R, WV, PPT, true>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, ct, CN, 1, 8);
+    fft_lds_ip<false, R, WV, PPT, true>(sm.a, p.r_ntt, 1, 1, 0, col_twt(sm, p), ct, CN, 1, 8);
   } else {
     stage_in<(PPT < 16 ? PPT : 16)>(sm.a, ntt, ct, CN, sample);
     sync_policy<WV>();
-    fft_lds_ip<false, R, WV, PPT>(sm.a, p.r_ntt, 1, 1, 0, sm.twt, ct, CN);
+    fft_lds_ip<false, R, WV, PPT>(sm.a, p.r_ntt, 1, 1, 0, col_twt(sm, p), ct, CN);
   }
   const cpx<R>* B = sm.a;
   if (ct < W) sm.a[ntt + ct] = sm.a[ct];
@@ -488,7 +508,7 @@ __device__ __forceinline__ void column_body(const KP& p, int ncol, int bx, const
       X[h3] = pol == 0 ? lo : (pol == 1 ? hi : (lo + hi) * R(0.5));
     }
     sync_policy<WV>();
-    fft_lds_ip<true, R, WV, PPT>(X, p.r_N3, 1, 1, 0, sm.tw3, ct, CN);
+    fft_lds_ip<true, R, WV, PPT>(X, p.r_N3, 1, 1, 0, col_tw3(sm, p), ct, CN);
     const cpx<R>* Zr = X;
     if (act) {
       cpx<R>* z1 = static_cast<cpx<R>*>(out) + col * N3;
@@ -524,8 +544,7 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
   const int ct = tid % CN, cw = tid / CN;
   const int ntt = p.ntt, N3 = p.N3, Nt = p.Nt, h3 = N3 / 2;
   ColSmem<R> sm = col_carve<R>(smem, p, cw, true);
-  load_twiddles(sm.twt, static_cast<const cpx<R>*>(p.tw_ntt), ntt, tid, nth);
-  load_twiddles(sm.tw3, static_cast<const cpx<R>*>(p.tw_N3), N3, tid, nth);
+  col_twiddles(sm, p, tid, nth);
   __syncthreads();
   // a column past the end of the list, or one the half-spectrum inverse
   // leaves out, runs the same steps on zeros (every barrier is reached) and
@@ -546,7 +565,7 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
   stage_in<(PPT < 16 ? PPT : 16)>(sm.a, N3, ct, CN, [&](int i) { return act ? zc[i] : cpx<R>{R(0), R(0)}; });
   sync_policy<WV>();
   // transpose of the unnormalised depth inverse: forward FFT
-  fft_lds_ip<false, R, WV, PPT>(sm.a, p.r_N3, 1, 1, 0, sm.tw3, ct, CN);
+  fft_lds_ip<false, R, WV, PPT>(sm.a, p.r_N3, 1, 1, 0, col_tw3(sm, p), ct, CN);
   const cpx<R>* Xp = sm.a;
   const int j1 = je - p.N1 / 2;
   const double a = double(j1) * double(j1) * p.inv_L1sq + double(k2) * double(k2) * p.inv_L2sq;
@@ -597,46 +616,29 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
   // the points' grid cells span [qlo, qhi]; an image of the time grid whose
   // tap window misses that span has no contribution
   const int qlo = sm.q0[0], qhi = sm.q0[npt - 1];
-  // st[v] = number of points with q0 < qlo + v (v in [0, span + 1]): a count
-  // per grid cell with integer LDS atomics (the counts do not depend on their
-  // order) and an inclusive prefix sum over the counts stored one cell up,
-  // taken by the column's first wavefront; the bounds of a tap window are
-  // then single reads. A span beyond the table (aliased frequencies) keeps
-  // the binary search.
+  // st[v] = number of points with q0 < qlo + v (v in [0, span + 1]). The
+  // points' cells q0 are non-decreasing, so st[v] = e for the cells v in
+  // (q0[e-1] - qlo, q0[e] - qlo]: each lane fills the cells between its
+  // point and the one before (no atomics, no scan), 16-bit entries (npt <=
+  // 4098). The bounds of a tap window are then single reads. A span beyond
+  // the table (aliased frequencies) keeps the binary search.
   const int span = qhi - qlo;
   const bool table = span <= ntt;
-  int* st = sm.st;
+  short* st = sm.st;
   if (table) {
-    for (int v = ct; v <= span + 1; v += CN) st[v] = 0;
-    sync_policy<WV>();
-    for (int e = ct; e < npt; e += CN) atomicAdd(&st[sm.q0[e] - qlo + 1], 1);
-    sync_policy<WV>();
-    if (ct < 64) {
-      const int lane = ct;
-      const int nv = span + 2, ch = (nv + 63) / 64;
-      const int v0 = lane * ch < nv ? lane * ch : nv;
-      const int v1 = v0 + ch < nv ? v0 + ch : nv;
-      int run = 0;
-      for (int v = v0; v < v1; ++v) run += st[v];
-      int incl = run;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int t = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += t;
-      }
-      int acc = incl - run;
-      for (int v = v0; v < v1; ++v) {
-        acc += st[v];
-        st[v] = acc;
-      }
+    for (int e = ct; e < npt; e += CN) {
+      const int hv = sm.q0[e] - qlo;
+      const int lv = e == 0 ? 0 : sm.q0[e - 1] - qlo + 1;
+      for (int v = lv; v <= hv; ++v) st[v] = short(e);
     }
+    if (ct == 0) st[span + 1] = short(npt);
     sync_policy<WV>();
   }
   // first point with q0 >= t
   auto lower = [&](int t, int from) {
     if (!table) return lower_bound_i(sm.q0, from, npt, t);
     const int v = t - qlo;
-    return v <= 0 ? 0 : (v > span ? npt : st[v]);
+    return v <= 0 ? 0 : (v > span ? npt : int(st[v]));
   };
   // the transform buffer is not read here (the loop reads the per-point
   // arrays and the table), so each B' value goes straight into it
@@ -660,7 +662,7 @@ __device__ __forceinline__ void column_adj_body(const KP& p, int ncol, int mwrap
     Bp[q] = acc;
   }
   sync_policy<WV>();
-  fft_lds_ip<true, R, WV, PPT>(Bp, p.r_ntt, 1, 1, 0, sm.twt, ct, CN);
+  fft_lds_ip<true, R, WV, PPT>(Bp, p.r_ntt, 1, 1, 0, col_twt(sm, p), ct, CN);
   const cpx<R>* Ap = Bp;
   if (act) {
     for (int n = ct; n < Nt; n += CN) {
