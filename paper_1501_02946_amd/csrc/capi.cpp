@@ -804,13 +804,20 @@ nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* ou
       for (int64_t m = 0; m < desc->m; ++m)
         start[size_t(G.cell[2 * size_t(m) + 1]) * n1 + size_t(G.cell[2 * size_t(m)]) + 1]++;
       for (size_t i = 0; i < n1 * n2; ++i) start[i + 1] += start[i];
-      std::vector<int> beg(n2 * (n1 + 1));
+      // the bounds table is padded by GPAD entries before and after (the
+      // sweep reads the bounds of whole blocks of cell rows, which reach past
+      // a column's range), the sensor table by two entries (read ahead)
+      constexpr size_t GPAD = 64;
+      std::vector<int> beg(n2 * (n1 + 1) + 2 * GPAD, 0);
       for (size_t c2 = 0; c2 < n2; ++c2)
-        for (size_t c1 = 0; c1 <= n1; ++c1) beg[c2 * (n1 + 1) + c1] = start[c2 * n1 + c1];
+        for (size_t c1 = 0; c1 <= n1; ++c1) beg[GPAD + c2 * (n1 + 1) + c1] = start[c2 * n1 + c1];
       std::vector<int> pos(start.begin(), start.end() - 1);
       for (int64_t m = 0; m < desc->m; ++m)
         colm[size_t(pos[size_t(G.cell[2 * size_t(m) + 1]) * n1 + size_t(G.cell[2 * size_t(m)])]++)] = int(m);
-      k.gcolbeg = static_cast<const int*>(A.upload(beg));
+      colm.push_back(0);
+      colm.push_back(0);
+      const int* bdev = static_cast<const int*>(A.upload(beg));
+      k.gcolbeg = bdev ? bdev + GPAD : nullptr;
       k.gcolm = static_cast<const int*>(A.upload(colm));
       k.gS = sweep_gather_ok(k) ? 128 : 0;
     }

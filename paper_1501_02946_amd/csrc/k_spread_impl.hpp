@@ -499,8 +499,24 @@ __global__ __launch_bounds__(256) void k_gather_sweep(KP p, const int* __restric
   for (int k = 0; k < W; ++k) soff[k] = pmod(c2 - W / 2 + 1 + k, n2) * Nt * 4;
   R ring[RS][W];
   const int Qa = S0 - W / 2 + 1, Qb = S1 - 1 + W / 2;
+  // scalar pipeline: the sensor index and both weight rows of the next
+  // sensor are loaded while the current one is summed, the index of the one
+  // after that a sensor earlier (the sensor table is padded past its end);
+  // the list bounds of a block's RS cell rows come in one batch of scalar
+  // loads per block (the bounds table is padded around every column's range)
   int e = cb[S0];
+  int m_next = colm[e];
+  int m_after = colm[e + 1];
+  WT w1n[W], w2n[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    w1n[k] = w1t[(size_t)m_next * W + k];
+    w2n[k] = w2t[(size_t)m_next * W + k];
+  }
   for (int q0 = floor_div(Qa, RS) * RS; q0 <= Qb + P; q0 += RS) {
+    int cbv[RS];
+#pragma unroll
+    for (int r = 0; r < RS; ++r) cbv[r] = cb[q0 + r - P - W / 2 + 1];
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
       const int q1 = q0 + r;
@@ -510,11 +526,27 @@ __global__ __launch_bounds__(256) void k_gather_sweep(KP p, const int* __restric
       // row q1 - RS, which no sensor needs any more
       const int V = q1 - P - W / 2;
       if (V >= S0 && V < S1) {
-        const int e_end = cb[V + 1];
+        const int e_end = cbv[r];
         for (; e < e_end; ++e) {
-          const int m = __builtin_amdgcn_readfirstlane(colm[e]);
-          const WT* __restrict__ w1 = w1t + (size_t)m * W;
-          const WT* __restrict__ w2 = w2t + (size_t)m * W;
+          // wait for this sensor's scalar loads, and issue the next ones only
+          // after the wait (a scalar load issued before it would be waited
+          // for as well; lgkmcnt(0), vmcnt and expcnt untouched)
+          __builtin_amdgcn_s_waitcnt(0xC07F);
+          __builtin_amdgcn_sched_barrier(0);
+          const int m = __builtin_amdgcn_readfirstlane(m_next);
+          WT w1[W], w2[W];
+#pragma unroll
+          for (int k = 0; k < W; ++k) {
+            w1[k] = w1n[k];
+            w2[k] = w2n[k];
+          }
+          m_next = m_after;
+#pragma unroll
+          for (int k = 0; k < W; ++k) {
+            w1n[k] = w1t[(size_t)m_next * W + k];
+            w2n[k] = w2t[(size_t)m_next * W + k];
+          }
+          m_after = colm[e + 2];
           A acc = A(0), cmp = A(0);
 #pragma unroll
           for (int k1 = 0; k1 < W; ++k1) {
