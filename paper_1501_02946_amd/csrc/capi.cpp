@@ -792,28 +792,32 @@ nedner_status create_one(const nedner_desc* desc_in, int device, nedner_plan* ou
       return x < y;
     });
     k.gorder = static_cast<const int*>(A.upload(order));
-    // the sweep gather's tables: the sensors of each second-axis cell column
-    // by first-axis cell (a counting sort: index order within a cell)
+    // the sweep gather's tables: the sensors of each pair of second-axis cell
+    // columns (2c, 2c + 1) by first-axis cell (a counting sort: index order
+    // within a cell), each entry 2 m + (c2 - 2c)
     const size_t n1 = size_t(v.n1), n2 = size_t(v.n2);
     bool in_grid = true;
     for (int64_t m = 0; m < desc->m && in_grid; ++m)
       in_grid = G.cell[2 * size_t(m)] >= 0 && size_t(G.cell[2 * size_t(m)]) < n1 &&
                 G.cell[2 * size_t(m) + 1] >= 0 && size_t(G.cell[2 * size_t(m) + 1]) < n2;
     if (in_grid) {
-      std::vector<int> start(n1 * n2 + 1, 0), colm(size_t(desc->m));
+      const size_t np2 = (n2 + 1) / 2;
+      std::vector<int> start(n1 * np2 + 1, 0), colm(size_t(desc->m));
       for (int64_t m = 0; m < desc->m; ++m)
-        start[size_t(G.cell[2 * size_t(m) + 1]) * n1 + size_t(G.cell[2 * size_t(m)]) + 1]++;
-      for (size_t i = 0; i < n1 * n2; ++i) start[i + 1] += start[i];
+        start[size_t(G.cell[2 * size_t(m) + 1] / 2) * n1 + size_t(G.cell[2 * size_t(m)]) + 1]++;
+      for (size_t i = 0; i < n1 * np2; ++i) start[i + 1] += start[i];
       // the bounds table is padded by GPAD entries before and after (the
       // sweep reads the bounds of whole blocks of cell rows, which reach past
       // a column's range), the sensor table by two entries (read ahead)
       constexpr size_t GPAD = 64;
-      std::vector<int> beg(n2 * (n1 + 1) + 2 * GPAD, 0);
-      for (size_t c2 = 0; c2 < n2; ++c2)
+      std::vector<int> beg(np2 * (n1 + 1) + 2 * GPAD, 0);
+      for (size_t c2 = 0; c2 < np2; ++c2)
         for (size_t c1 = 0; c1 <= n1; ++c1) beg[GPAD + c2 * (n1 + 1) + c1] = start[c2 * n1 + c1];
       std::vector<int> pos(start.begin(), start.end() - 1);
-      for (int64_t m = 0; m < desc->m; ++m)
-        colm[size_t(pos[size_t(G.cell[2 * size_t(m) + 1]) * n1 + size_t(G.cell[2 * size_t(m)])]++)] = int(m);
+      for (int64_t m = 0; m < desc->m; ++m) {
+        const int c2 = G.cell[2 * size_t(m) + 1];
+        colm[size_t(pos[size_t(c2 / 2) * n1 + size_t(G.cell[2 * size_t(m)])]++)] = int(2 * m + (c2 & 1));
+      }
       colm.push_back(0);
       colm.push_back(0);
       const int* bdev = static_cast<const int*>(A.upload(beg));

@@ -441,20 +441,21 @@ __global__ __launch_bounds__(256) void k_gather(KP p, const R* __restrict__ U, R
 }
 
 // Transpose of the spreading as a sweep along the first axis, the mirror of
-// the forward sweep: a wavefront owns one second-axis cell column c2 (the
-// sensors whose window starts in it all read the same W grid columns), one
-// segment of first-axis cell rows [S0, S1) and 64 time samples (one per lane,
-// coalesced). It walks the grid rows in order, keeping the last RS rows of its
-// W columns in registers (a ring, every index compile-time by unrolling the
-// walk by RS), and loads each row P = RS - W steps before the first sensor
-// that needs it, so the loads of P rows are in flight while the sensors of
-// earlier rows are summed. A sensor of cell row V is summed P steps after row
-// V + W/2 was loaded: all its W x W taps are then in the ring. Each grid value is loaded once per
-// cell column whose window covers it, from L2 (neighbouring columns share
-// their rows there), and every tap of every sensor is read from registers.
-// The terms are added in the order of the tile-staged gather (the W taps of a
-// row in R, then the W row sums in A, with KAHAN compensated), so both give
-// the same values.
+// the forward sweep: a wavefront owns a pair of second-axis cell columns
+// (2c, 2c + 1: the sensors whose windows start there read W + 1 grid
+// columns), one segment of first-axis cell rows [S0, S1) and 64 time samples
+// (one per lane, coalesced). It walks the grid rows in order, keeping the last
+// RS rows of its W + 1 columns in registers (a ring, every index compile-time
+// by unrolling the walk by RS), and loads each row P = RS - W steps before the
+// first sensor that needs it, so the loads of P rows are in flight while the
+// sensors of earlier rows are summed. A sensor of cell row V is summed P
+// steps after row V + W/2 was loaded: all its W x W taps are then in the ring
+// (at column offset 0 or 1 of the pair). Each grid value is loaded once per
+// column pair whose windows cover it, from L2 (neighbouring pairs share their
+// rows there), and every tap of every sensor is read from registers. The
+// terms are added in the order of the tile-staged gather (the W taps of a row
+// in R, then the W row sums in A, with KAHAN compensated), so both give the
+// same values.
 template <int W, int RS, typename R, typename WT, typename A, bool KAHAN>
 __global__ __launch_bounds__(256) void k_gather_sweep(KP p, const int* __restrict__ colbeg,
                                                       const int* __restrict__ colm,
@@ -462,9 +463,11 @@ __global__ __launch_bounds__(256) void k_gather_sweep(KP p, const int* __restric
                                                       const WT* __restrict__ w2t,
                                                       const R* __restrict__ U, R* __restrict__ g) {
   constexpr int P = RS - W;
+  constexpr int WC = W + 1;  // grid columns of a cell-column pair
   static_assert(P >= 0, "the ring holds at least the W rows of a sensor");
   const int n1 = p.n1, n2 = p.n2, Nt = p.Nt;
-  const int ngrp = (n2 + 3) >> 2;
+  const int npair = (n2 + 1) >> 1;
+  const int ngrp = (npair + 3) >> 2;
   const int nsg = (n1 + p.gS - 1) / p.gS;
   const int nch = (Nt + 63) >> 6;
   const int G = ngrp * nsg * nch;
@@ -479,74 +482,85 @@ __global__ __launch_bounds__(256) void k_gather_sweep(KP p, const int* __restric
   const int sg = rest % nsg;
   const int chunk = rest / nsg;
   const int lane = threadIdx.x & 63;
-  const int c2 = __builtin_amdgcn_readfirstlane(grp * 4 + (threadIdx.x >> 6));
-  if (c2 >= n2) return;
+  const int cp = __builtin_amdgcn_readfirstlane(grp * 4 + (threadIdx.x >> 6));
+  if (cp >= npair) return;
   const int S0 = sg * p.gS;
   const int S1 = S0 + p.gS < n1 ? S0 + p.gS : n1;
   const int t = chunk * 64 + lane;
   const bool tok = t < Nt;
   // lanes past the end read sample 0 (a valid address) and store nothing
   const unsigned toff = tok ? unsigned(t) : 0u;
-  const int* __restrict__ cb = colbeg + (size_t)c2 * (n1 + 1);
+  const int* __restrict__ cb = colbeg + (size_t)cp * (n1 + 1);
   // rows are read with buffer loads: a scalar resource per grid row (its
   // n2 Nt samples), a scalar byte offset per column and one vector byte
   // offset for the lane, so that no load needs a 64-bit vector address
   static_assert(sizeof(R) == 4, "the sweep gather reads 32-bit samples");
   const int rowbytes = n2 * Nt * 4;
   const int voff = int(toff) * 4;
-  int soff[W];
+  int soff[WC];
 #pragma unroll
-  for (int k = 0; k < W; ++k) soff[k] = pmod(c2 - W / 2 + 1 + k, n2) * Nt * 4;
-  R ring[RS][W];
+  for (int k = 0; k < WC; ++k) soff[k] = pmod(2 * cp - W / 2 + 1 + k, n2) * Nt * 4;
+  R ring[RS][WC];
   const int Qa = S0 - W / 2 + 1, Qb = S1 - 1 + W / 2;
-  // scalar pipeline: the sensor index and both weight rows of the next
-  // sensor are loaded while the current one is summed, the index of the one
-  // after that a sensor earlier (the sensor table is padded past its end);
-  // the list bounds of a block's RS cell rows come in one batch of scalar
-  // loads per block (the bounds table is padded around every column's range)
+  // scalar pipeline: the sensor entry (2 m + column offset) and both weight
+  // rows of the next sensor are loaded while the current one is summed, the
+  // entry of the one after that a sensor earlier (the sensor table is padded
+  // past its end); the list bound of a step's cell row is read a step
+  // ahead (the bounds table is padded around every pair's range)
   int e = cb[S0];
-  int m_next = colm[e];
-  int m_after = colm[e + 1];
+  int v_next = colm[e];
+  int v_after = colm[e + 1];
   WT w1n[W], w2n[W];
 #pragma unroll
   for (int k = 0; k < W; ++k) {
-    w1n[k] = w1t[(size_t)m_next * W + k];
-    w2n[k] = w2t[(size_t)m_next * W + k];
+    w1n[k] = w1t[(size_t)(v_next >> 1) * W + k];
+    w2n[k] = w2t[(size_t)(v_next >> 1) * W + k];
   }
+  // the list bound of the next step's cell row, read a step ahead
+  int cb_next = cb[floor_div(Qa, RS) * RS - P - W / 2 + 1];
   for (int q0 = floor_div(Qa, RS) * RS; q0 <= Qb + P; q0 += RS) {
-    int cbv[RS];
-#pragma unroll
-    for (int r = 0; r < RS; ++r) cbv[r] = cb[q0 + r - P - W / 2 + 1];
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
       const int q1 = q0 + r;
+      const int e_end = cb_next;
+      cb_next = cb[q1 - P - W / 2 + 2];
       if (q1 < Qa || q1 > Qb + P) continue;
       // first the sensors whose last row is q1 - P (the newest of their rows
       // was loaded P steps ago), then the loads of row q1 into the slot of
       // row q1 - RS, which no sensor needs any more
       const int V = q1 - P - W / 2;
       if (V >= S0 && V < S1) {
-        const int e_end = cbv[r];
         for (; e < e_end; ++e) {
           // wait for this sensor's scalar loads, and issue the next ones only
           // after the wait (a scalar load issued before it would be waited
           // for as well; lgkmcnt(0), vmcnt and expcnt untouched)
           __builtin_amdgcn_s_waitcnt(0xC07F);
           __builtin_amdgcn_sched_barrier(0);
-          const int m = __builtin_amdgcn_readfirstlane(m_next);
+          const int v = __builtin_amdgcn_readfirstlane(v_next);
           WT w1[W], w2[W];
 #pragma unroll
           for (int k = 0; k < W; ++k) {
             w1[k] = w1n[k];
             w2[k] = w2n[k];
           }
-          m_next = m_after;
+          v_next = v_after;
 #pragma unroll
           for (int k = 0; k < W; ++k) {
-            w1n[k] = w1t[(size_t)m_next * W + k];
-            w2n[k] = w2t[(size_t)m_next * W + k];
+            w1n[k] = w1t[(size_t)(v_next >> 1) * W + k];
+            w2n[k] = w2t[(size_t)(v_next >> 1) * W + k];
           }
-          m_after = colm[e + 2];
+          v_after = colm[e + 2];
+          // the second-axis weights placed at the sensor's column offset in
+          // the pair (a zero weight on the other end): one code path for both
+          // columns, the extra term adds zero exactly
+          const bool odd = (v & 1) != 0;
+          WT w2e[WC];
+#pragma unroll
+          for (int k = 0; k < WC; ++k) {
+            const WT lo = k < W ? w2[k] : WT(0);
+            const WT hi = k > 0 ? w2[k - 1] : WT(0);
+            w2e[k] = odd ? hi : lo;
+          }
           A acc = A(0), cmp = A(0);
 #pragma unroll
           for (int k1 = 0; k1 < W; ++k1) {
@@ -554,7 +568,7 @@ __global__ __launch_bounds__(256) void k_gather_sweep(KP p, const int* __restric
             const int sl = (r + 1 + k1) % RS;
             R ra = R(0);
 #pragma unroll
-            for (int k2 = 0; k2 < W; ++k2) ra += R(w2[k2]) * ring[sl][k2];
+            for (int k2 = 0; k2 < WC; ++k2) ra += R(w2e[k2]) * ring[sl][k2];
             const A wk = A(w1[k1]);
             if constexpr (KAHAN) {
               const A y = fmaf(wk, A(ra), -cmp);
@@ -565,14 +579,15 @@ __global__ __launch_bounds__(256) void k_gather_sweep(KP p, const int* __restric
               acc += wk * A(ra);
             }
           }
-          if (tok) g[(size_t)m * Nt + t] = KAHAN ? R(acc - cmp) : R(acc);
+          const R out = KAHAN ? R(acc - cmp) : R(acc);
+          if (tok) g[(size_t)(v >> 1) * Nt + t] = out;
         }
       }
       if (q1 <= Qb) {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<R*>(U + (size_t)pmod(q1, n1) * n2 * Nt), (short)0, rowbytes, 0x00020000);
 #pragma unroll
-        for (int k = 0; k < W; ++k)
+        for (int k = 0; k < WC; ++k)
           ring[r][k] = __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff[k], 0));
       }
     }
@@ -591,7 +606,7 @@ static hipError_t gather_sweep_w(const KP& p, const void* U, void* g, hipStream_
   if constexpr (RS == 0) {
     return hipErrorInvalidValue;
   } else {
-    const long G = (long)((p.n2 + 3) / 4) * ((p.n1 + p.gS - 1) / p.gS) * ((p.Nt + 63) / 64);
+    const long G = (long)(((p.n2 + 1) / 2 + 3) / 4) * ((p.n1 + p.gS - 1) / p.gS) * ((p.Nt + 63) / 64);
     hipLaunchKernelGGL((k_gather_sweep<W, RS, R, WT, A, KAHAN>), dim3(unsigned(8 * ((G + 7) / 8))), dim3(256), 0, s,
                        p, p.gcolbeg, p.gcolm, static_cast<const WT*>(p.w1), static_cast<const WT*>(p.w2),
                        static_cast<const R*>(U), static_cast<R*>(g));
