@@ -276,8 +276,11 @@ __device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, 
 // (the earlier stages done by the caller, see stage_first_ip).
 // PAD (single lines only): the line arrives in the swizzled layout and every
 // stage but the last keeps it; the last writes the plain layout.
+// Always inlined: as a called function its per-stage register arrays would
+// live in scratch memory (the compiler declines to inline it into the
+// largest column kernels otherwise).
 template <bool INV, typename T, bool WAVE, int PPT, bool PAD = false, typename TWT = const cpx<T>*>
-__device__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, int ls, const TWT& tw,
+__device__ __forceinline__ void fft_lds_ip(cpx<T>* buf, const Radices& rd, int lines, int ps, int ls, const TWT& tw,
                            int tid, int nth, int s0 = 0, int Ns0 = 1) {
   int Ns = Ns0;
   for (int s = s0; s < rd.count; ++s) {
