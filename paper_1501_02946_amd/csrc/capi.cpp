@@ -1045,6 +1045,10 @@ nedner_status create_batch(const nedner_desc* descs, int count, int device, nedn
   for (int i = 0; i < count; ++i) {
     nedner_desc d = descs[i];
     d.time_per_lane = TT;
+    // the problems of a batch share the chip: long sweeps (less overlap work)
+    // beat the short ones a problem alone needs to fill it (the batch
+    // autotuner picks 256 rows, clamped to each grid, on the 64-problem set)
+    if (d.rows_per_wave == 0) d.rows_per_wave = 256;
     nedner_plan sp = nullptr;
     nedner_status st = create_one(&d, device, &sp);
     if (st != NEDNER_OK) {

@@ -44,7 +44,8 @@ def test_batch_matches_oracle_and_single_plans(torch_gpu, prec):
         ref = O.forward(p.xy, p.h, p.g, geometry_of(p))
         err = rel_l2(o, ref)
         single = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), c=p.c, h=p.h, t0=p.t0, a1=p.a1,
-                        a2=p.a2, d1=p.d1, d2=p.d2, d3=p.d3, precision=prec, time_per_lane=2)
+                        a2=p.a2, d1=p.d1, d2=p.d2, d3=p.d3, precision=prec, time_per_lane=2,
+                        rows_per_wave=256)  # the batch's default sweep (clamped to the grid)
         so = single(g).cpu().numpy()
         print(prec, p.m, p.nt, (p.n1, p.n2, p.n3), "batch vs oracle", err, "bitwise", np.array_equal(so, o))
         assert err <= 1e-5
@@ -67,7 +68,7 @@ def test_c4_batch_64_problems(torch_gpu):
     for i in (0, 17, 63):
         p = probs[i]
         single = N.Plan(p.xy, p.nt, p.dt, (p.n1, p.n2, p.n3), h=p.h, precision="fp32c",
-                        time_per_lane=4)
+                        time_per_lane=4, rows_per_wave=256)
         assert np.array_equal(single(gs[i]).cpu().numpy(), outs[i].cpu().numpy())
     p = probs[5]
     ref = O.forward(p.xy, p.h, p.g, geometry_of(p))
