@@ -57,12 +57,18 @@ __device__ __forceinline__ cpx<R>* pass_fft(Smem<R>& sm, const Radices& rd, int 
 // the neighbouring tiles along the contiguous axis, which share cache lines
 // at their edges, run under the same L2. Returns false past the last tile.
 // The first-axis passes (lat_b, adj_b), whose lines are K2 Nt points apart,
-// measured faster in plain launch order (REMAP false): there the tile is
-// blockIdx.x itself.
-template <bool REMAP = true>
+// measured faster in launch order (REMAP false) than in contiguous runs.
+// PAIR (lateral pass B and its transpose): launch order, except that the
+// two tiles of each consecutive pair go to one XCD: their 64-byte rows are
+// the two halves of the same cache lines, which one L2 then fetches once,
+// while the chip as a whole still streams one region of the array at a time.
+// The grid is a multiple of 16 workgroups.
+template <bool REMAP = true, bool PAIR = false>
 __device__ __forceinline__ bool xcd_tile(int gx, int ntile, int& bx, int& by) {
   const int per = (ntile + 7) >> 3;
-  const int L = REMAP ? (blockIdx.x & 7) * per + (blockIdx.x >> 3) : int(blockIdx.x);
+  const int b = int(blockIdx.x);
+  const int L = REMAP ? (b & 7) * per + (b >> 3)
+                      : (PAIR ? (b & ~15) + ((b & 7) << 1) + ((b >> 3) & 1) : b);
   if (L >= ntile) return false;
   by = L / gx;
   bx = L - by * gx;
@@ -143,7 +149,7 @@ template <typename R, bool IP>
 __global__ __launch_bounds__(512) void k_lat_b(KP p, int TB, int gx, int ntile, const cpx<R>* __restrict__ V,
                                                cpx<R>* __restrict__ G) {
   int bx, by;
-  if (!xcd_tile<false>(gx, ntile, bx, by)) return;
+  if (!xcd_tile<false, true>(gx, ntile, bx, by)) return;
   lat_b_body<R, IP>(p, TB, bx, by, V, G);
 }
 
@@ -341,7 +347,7 @@ template <typename R, bool IP>
 __global__ __launch_bounds__(512) void k_adj_b(KP p, int TB, int gx, int ntile, const cpx<R>* __restrict__ G,
                                                cpx<R>* __restrict__ V) {
   int bx, by;
-  if (!xcd_tile<false>(gx, ntile, bx, by)) return;
+  if (!xcd_tile<false, true>(gx, ntile, bx, by)) return;
   adj_b_body<R, IP>(p, TB, bx, by, G, V);
 }
 
@@ -430,7 +436,7 @@ static size_t smem_for(int n, int TB, bool ip) {
     const int nth = pass_threads_for(p, n, TB);                                                 \
     const size_t sh = smem_for<R>(n, TB, ip);                                                   \
     const int gx = ((GYLINES) + TB - 1) / TB, ntile = gx * (GX);                                \
-    dim3 grid(8 * ((ntile + 7) / 8));                                                           \
+    dim3 grid(16 * ((ntile + 15) / 16));                                                        \
     hipError_t e = ip ? allow_smem(KERNEL<R, true>, sh) : allow_smem(KERNEL<R, false>, sh);     \
     if (e != hipSuccess) return e;                                                              \
     if (ip)                                                                                     \
