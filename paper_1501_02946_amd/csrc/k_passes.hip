@@ -199,22 +199,36 @@ __device__ __forceinline__ void pass_d_body(const KP& p, int TB, int bx, int by,
   const int i1 = by, pb = bx * TB, N3 = p.N3, npairs = N3 / 2, h = n / 2;
   load_twiddles(sm.tw, static_cast<const cpx<R>*>(p.tw_N2), n, tid, nth);
   const int lsh = __builtin_ctz(TB);
-  stage_in<8>(sm.a, n * TB, tid, nth, [&](int i) {
-    const int k = i >> lsh, pr = pb + (i & (TB - 1));
-    cpx<R> c = {R(0), R(0)};
-    if (pr < npairs) {
-      const int kk = k <= h ? k : n - k;
-      const size_t o = ((size_t)kk * p.N1 + i1) * N3 + 2 * pr;
-      const cpx<R> za = Z2[o], zb = Z2[o + 1];
-      if (k == 0 || k == h)
-        c = {za.x, zb.x};
-      else if (k < h)
-        c = {za.x - zb.y, za.y + zb.x};
-      else
-        c = {za.x + zb.y, zb.x - za.y};
+  // each half-spectrum bin k = 0..n/2 is read once and feeds bins k and
+  // n - k (the real bins 0 and n/2 take the two packed depth lines on one bin)
+  constexpr int BATCH = 4;
+  const int total = (h + 1) * TB;
+  for (int base = 0; base < total; base += BATCH * nth) {
+    cpx<R> za[BATCH], zb[BATCH];
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int i = base + tid + q * nth;
+      const int k = i >> lsh, pr = pb + (i & (TB - 1));
+      za[q] = zb[q] = cpx<R>{R(0), R(0)};
+      if (i < total && pr < npairs) {
+        const size_t o = ((size_t)k * p.N1 + i1) * N3 + 2 * pr;
+        za[q] = Z2[o];
+        zb[q] = Z2[o + 1];
+      }
     }
-    return c;
-  });
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int i = base + tid + q * nth;
+      if (i >= total) continue;
+      const int k = i >> lsh, pp = i & (TB - 1);
+      if (k == 0 || k == h) {
+        sm.a[k * TB + pp] = cpx<R>{za[q].x, zb[q].x};
+      } else {
+        sm.a[k * TB + pp] = cpx<R>{za[q].x - zb[q].y, za[q].y + zb[q].x};
+        sm.a[(n - k) * TB + pp] = cpx<R>{za[q].x + zb[q].y, zb[q].x - za[q].y};
+      }
+    }
+  }
   __syncthreads();
   cpx<R>* Z = pass_fft<true, R, IP>(sm, p.r_N2, TB, tid, nth);
   R* dst = vol + (size_t)i1 * n * N3;
