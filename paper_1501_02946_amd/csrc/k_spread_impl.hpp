@@ -196,6 +196,27 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
   }
   WT w2n = ew[e];
   int mn = em[e + 1];
+  // float sums: the samples of the next entry are read from the staging
+  // buffer during this entry's multiply-adds, so that the wait at the next
+  // entry finds them there; the four scaled samples take the registers the
+  // read needs first (double sums keep one scaled sample at a time)
+  constexpr bool PRE = sizeof(A) == 4;
+  auto stage_batch = [&]() {
+#pragma unroll
+    for (int j = 0; j < BE; ++j)
+#pragma unroll
+      for (int t = 0; t < TT; ++t) stg[j * 64 * TT + t] = nx[j][t];
+    nb += BE;
+    issue(nb);
+  };
+  R gn[TT];
+  if constexpr (PRE) {
+    if (e < eall) {
+      stage_batch();
+#pragma unroll
+      for (int t = 0; t < TT; ++t) gn[t] = stg[(e - (nb - BE)) * 64 * TT + t];
+    }
+  }
   for (int c0 = floor_div(Vstart, W) * W; c0 <= Vend; c0 += W) {
 #pragma unroll
     for (int r = 0; r < W; ++r) {
@@ -203,18 +224,16 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
       if (V < Vstart || V > Vend) continue;
       const int stop = cb[V - Vstart + 1];
       while (e < stop) {
-        if (e == nb) {
-#pragma unroll
-          for (int j = 0; j < BE; ++j)
-#pragma unroll
-            for (int t = 0; t < TT; ++t) stg[j * 64 * TT + t] = nx[j][t];
-          nb += BE;
-          issue(nb);
-        }
-        const int j = e - (nb - BE);
         R gv[TT];
+        if constexpr (PRE) {
 #pragma unroll
-        for (int t = 0; t < TT; ++t) gv[t] = stg[j * 64 * TT + t];
+          for (int t = 0; t < TT; ++t) gv[t] = gn[t];
+        } else {
+          if (e == nb) stage_batch();
+          const int j = e - (nb - BE);
+#pragma unroll
+          for (int t = 0; t < TT; ++t) gv[t] = stg[j * 64 * TT + t];
+        }
         WT wc[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) wc[k] = wn[k];
@@ -228,15 +247,33 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
         for (int k = 0; k < W; ++k) wn[k] = w1t[(size_t)mn * W + k];
         w2n = ew[e + 1];
         mn = em[e + 2];
-        // one time sample at a time: two registers for the scaled sample
-        // instead of 2 TT keep the kernel within four wavefronts per SIMD
+        if constexpr (PRE) {
+          A gt[TT];
 #pragma unroll
-        for (int t = 0; t < TT; ++t) {
-          const A gt = A(gv[t]) * A(w2c);
+          for (int t = 0; t < TT; ++t) gt[t] = A(gv[t]) * A(w2c);
+          // the next entry's samples (its batch staged first when it starts
+          // one; a read past the segment's last entry stays in the buffer)
+          if (e + 1 == nb) stage_batch();
 #pragma unroll
-          for (int k = 0; k < W; ++k) {
-            const int sl = (r + k + W / 2 + 1) % W;
-            acc[sl][t] += A(wc[k]) * gt;
+          for (int t = 0; t < TT; ++t) gn[t] = stg[(e + 1 - (nb - BE)) * 64 * TT + t];
+#pragma unroll
+          for (int t = 0; t < TT; ++t)
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+              const int sl = (r + k + W / 2 + 1) % W;
+              acc[sl][t] += A(wc[k]) * gt[t];
+            }
+        } else {
+          // one time sample at a time: two registers for the scaled sample
+          // instead of 2 TT keep the kernel within four wavefronts per SIMD
+#pragma unroll
+          for (int t = 0; t < TT; ++t) {
+            const A gt = A(gv[t]) * A(w2c);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+              const int sl = (r + k + W / 2 + 1) % W;
+              acc[sl][t] += A(wc[k]) * gt;
+            }
           }
         }
         ++e;
