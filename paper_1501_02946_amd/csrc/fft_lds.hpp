@@ -58,15 +58,25 @@ struct TwHalf {
   int mul;  // index stride into the table
   int nh;   // entries held: half the table's length
 };
+// twstride: the factor an exponent i is scaled by into the table; twat: the
+// entry at an index already scaled (one lookup, the sign of the second half
+// applied by selects rather than a branch per lane).
+template <typename T>
+__device__ __forceinline__ int twstride(const cpx<T>*) { return 1; }
+template <typename T>
+__device__ __forceinline__ int twstride(const TwHalf<T>& tw) { return tw.mul; }
+template <typename T>
+__device__ __forceinline__ cpx<T> twat(const cpx<T>* tw, int ii) { return tw[ii]; }
+template <typename T>
+__device__ __forceinline__ cpx<T> twat(const TwHalf<T>& tw, int ii) {
+  const bool up = ii >= tw.nh;
+  const cpx<T> w = tw.t[up ? ii - tw.nh : ii];
+  return cpx<T>{up ? -w.x : w.x, up ? -w.y : w.y};
+}
 template <typename T>
 __device__ __forceinline__ cpx<T> twget(const cpx<T>* tw, int i) { return tw[i]; }
 template <typename T>
-__device__ __forceinline__ cpx<T> twget(const TwHalf<T>& tw, int i) {
-  const int ii = i * tw.mul;
-  if (ii < tw.nh) return tw.t[ii];
-  const cpx<T> w = tw.t[ii - tw.nh];
-  return cpx<T>{-w.x, -w.y};
-}
+__device__ __forceinline__ cpx<T> twget(const TwHalf<T>& tw, int i) { return twat(tw, i * tw.mul); }
 
 template <int R, bool INV, typename T>
 __device__ __forceinline__ void dft_small(cpx<T>* v) {
@@ -248,9 +258,11 @@ __device__ __forceinline__ void stage_ip(cpx<T>* buf, int n, int Ns, int lines, 
       const int b = t & (lines - 1), j = t >> lsh;
       const int k = ns_pow2 ? (j & (Ns - 1)) : (j % Ns);
       if (Ns > 1) {
+        // exponent r k tstep, scaled into the table once per butterfly
+        const int kt = k * (tstep * twstride(tw));
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cpx<T> w = twget(tw, r * k * tstep);
+          cpx<T> w = twat(tw, r * kt);
           v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
         }
       }

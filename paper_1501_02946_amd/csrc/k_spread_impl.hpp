@@ -107,7 +107,11 @@ __device__ __forceinline__ int pmod(int a, int n) {
 // Table pointers are separate __restrict__ parameters so that the compiler
 // knows they are read-only for the whole kernel and fetches the wave-uniform
 // ones (list entries, first-axis weights) through the scalar cache.
-template <int W, int TT, typename R, typename WT, typename A, bool VEC, bool KAHAN>
+// READ_AHEAD: read the next entry's samples during the current entry (float
+// sums only; the batched launch, whose per-problem fields take more
+// registers, stays without it: the four extra registers would cost it a
+// wavefront per SIMD).
+template <int W, int TT, typename R, typename WT, typename A, bool VEC, bool KAHAN, bool READ_AHEAD = true>
 __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const int* __restrict__ cellbeg,
                                                    const int* __restrict__ em, const WT* __restrict__ ew,
                                                    const WT* __restrict__ w1t, const R* __restrict__ g,
@@ -200,7 +204,7 @@ __device__ __forceinline__ void spread_body_staged(const KP& p, int bx, const in
   // buffer during this entry's multiply-adds, so that the wait at the next
   // entry finds them there; the four scaled samples take the registers the
   // read needs first (double sums keep one scaled sample at a time)
-  constexpr bool PRE = sizeof(A) == 4;
+  constexpr bool PRE = READ_AHEAD && sizeof(A) == 4;
   auto stage_batch = [&]() {
 #pragma unroll
     for (int j = 0; j < BE; ++j)
@@ -732,7 +736,7 @@ __global__ __launch_bounds__(256) void k_spread_many(const BatchProb* __restrict
   work_loop(wl, [&](int prob, int local) {
     const BatchProb& B = bp[prob];
     const KP& p = B.kp;
-    spread_body_staged<W, TT, R, WT, A, VEC, KAHAN>(p, local, p.cellbeg, p.ent_m,
+    spread_body_staged<W, TT, R, WT, A, VEC, KAHAN, false>(p, local, p.cellbeg, p.ent_m,
                                                     static_cast<const WT*>(p.ent_w2),
                                                     static_cast<const WT*>(p.w1), static_cast<const R*>(B.g),
                                                     static_cast<R*>(B.b0));
